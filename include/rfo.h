@@ -1,0 +1,155 @@
+/*
+ * rfo.h -- randomized Fermi-operator expansion on one MI355X (gfx950).
+ *
+ * C ABI of the hot path of the randomized Chebyshev method assessed in
+ * Moussa & Baczewski, "Assessment of localized and randomized algorithms for
+ * electronic structure" (arXiv:1812.05264).  For an orthogonal (S = I) sparse
+ * tight-binding Hamiltonian H, a temperature T and a chemical potential mu the
+ * library evaluates, from a block of probe vectors R = [r_1 ... r_s]:
+ *
+ *   moments   mu_{k,c} = r_c^T T_k(H_hat) r_c, k < p, with the spectral map
+ *             H_hat = (2H - (e_max + e_min) I)/(e_max - e_min)
+ *             (Polynomial approximation; Chebyshev recursion with S = I);
+ *   traces    N = tr f(H), E = tr[H f(H)], F = tr g(H), each as
+ *             sum_c w_c sum_k c_k mu_{k,c} with the Chebyshev coefficients c_k
+ *             of f, x f(x) or g (Methods: free-energy function g, Fermi
+ *             function f = g', free energy, electron count and band energy);
+ *   density   M (.) P~ = sum_c w_c M (.) (f(H) r_c r_c^T) on H's block
+ *             pattern M (Random approximation, random density estimator);
+ *   gradient  dF~/dH on H's block pattern for the probe estimate
+ *             F~ = sum_c w_c r_c^T g_p(H) r_c, by the reverse (Clenshaw)
+ *             form of the polynomial free-energy derivative (Analytical
+ *             free-energy derivatives), and from it Hellmann-Feynman forces
+ *             (Observable response, dF/dlambda = tr[P dH/dlambda]).
+ *
+ * Conventions shared by every call:
+ *   - All functions return an rfo_status.  Nothing is thrown across the ABI.
+ *     On failure rfo_last_error() describes the cause.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ *   - Every pointer belongs to the caller.  set_* calls copy their inputs, so
+ *     the caller may free them on return.  Output pointers may be host memory
+ *     or device memory of the context's GPU (unified addressing decides the
+ *     copy direction); a call returns only once its outputs are complete.
+ *   - Work is issued on the stream given to rfo_create (NULL = the null
+ *     stream), so the library interoperates with a PyTorch stream.
+ *   - Block-sparse row (BSR) layout, used by every H-shaped array:
+ *       row_ptr int64 [n_block_rows + 1], row_ptr[0] = 0, non-decreasing;
+ *       col_idx int32 [nnzb], strictly increasing inside a block row;
+ *       blocks  [nnzb][block_dim][block_dim] row-major;
+ *     block_dim is 1 or 9, every block row stores its diagonal block, the
+ *     pattern is symmetric and H_JI = H_IJ^T.
+ *   - Probe layout: R [n][s] row-major, n = n_block_rows * block_dim.
+ */
+#ifndef RFO_H
+#define RFO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rfo_ctx rfo_ctx;
+
+typedef enum {
+  RFO_OK = 0,
+  RFO_E_INVALID = -1,     /* bad argument, layout or pattern */
+  RFO_E_STATE = -2,       /* call out of order (e.g. moments before probes) */
+  RFO_E_NOMEM = -3,       /* device allocation failed */
+  RFO_E_DEVICE = -4,      /* HIP runtime error */
+  RFO_E_NUMERIC = -5,     /* non-finite input, or |mu_{k,c}| > ||r_c||^2:
+                             the spectrum left [e_min, e_max] */
+  RFO_E_UNSUPPORTED = -6  /* valid request the library does not implement */
+} rfo_status;
+
+/* Arithmetic of the H.V products (Chebyshev steps).  Spectral map, moments,
+ * traces and Chebyshev coefficients are always FP64. */
+typedef enum {
+  RFO_FP64 = 0,           /* FP64 vectors and H */
+  RFO_FP32 = 1,           /* FP32 vectors and H, FP64 moments */
+  RFO_BF16 = 2            /* BF16 H and vector operands on MFMA, FP32
+                             accumulation and FP32 vectors, FP64 moments */
+} rfo_precision;
+
+/* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t or
+ * NULL.  *out receives the context (NULL on failure). */
+int rfo_create(rfo_ctx **out, int device, void *hip_stream);
+
+/* Frees all device memory of the context.  NULL is ignored. */
+void rfo_destroy(rfo_ctx *ctx);
+
+/* Message of the last failed call on ctx ("" if none); valid until the next
+ * call on ctx.  With ctx == NULL: the message of the last failed rfo_create. */
+const char *rfo_last_error(const rfo_ctx *ctx);
+
+/* Sets H (paper: Methods, orthogonal basis S = I; Polynomial approximation,
+ * spectral interval [e_min, e_max]).  The library stores the mapped
+ * Hamiltonian H_hat = (2H - (e_max + e_min) I)/(e_max - e_min) in the
+ * requested precision.  If e_min >= e_max the interval is Gershgorin's,
+ * widened by 1% about its centre.
+ *   row_ptr, col_idx: host memory; values: host or device memory, FP64.
+ *   row_ptr == NULL && col_idx == NULL keeps the previous pattern and replaces
+ *   the values only (n_block_rows and block_dim must repeat).
+ * Errors: RFO_E_INVALID for a bad layout, a missing diagonal block, an
+ * asymmetric pattern or asymmetric values; RFO_E_NUMERIC for non-finite
+ * values. */
+int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim,
+                        const int64_t *row_ptr, const int32_t *col_idx,
+                        const double *values, double e_min, double e_max,
+                        int precision);
+
+/* Returns the spectral interval in use (after a Gershgorin fallback). */
+int rfo_get_interval(const rfo_ctx *ctx, double *e_min, double *e_max);
+
+/* Sets the probe block R [n][s] (host memory, FP64) and weights w [s]
+ * (host memory; NULL = 1/s each), so that sum_c w_c r_c r_c^T estimates the
+ * identity (Random approximation: mean of R R^dagger is I).  Probes whose
+ * entries are all +-1 (Rademacher) are stored as sign bits; any other real
+ * probes are stored in FP64.  Must follow rfo_set_hamiltonian (n must match);
+ * setting a new Hamiltonian of another size clears the probes. */
+int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R,
+                   const double *weights);
+
+/* Runs p = n_terms Chebyshev terms (p - 1 H.V steps) on every probe.
+ *   moments_out [s][p]  per-probe mu_{k,c} (nullable)
+ *   NEF_out     [3]     N, E, F (nullable)
+ *   density_out [nnzb][bd][bd]  M (.) P~, unsymmetrized (nullable; when NULL
+ *               the density accumulator is not run)
+ * Requires T > 0, finite mu, 1 <= n_terms <= 1048576.
+ * Errors: RFO_E_STATE without H or probes; RFO_E_NUMERIC when a moment
+ * exceeds ||r_c||^2 (relative slack 1e-6 in FP64, 1e-3 in FP32/BF16). */
+int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
+                      double *moments_out, double *NEF_out,
+                      double *density_out);
+
+/* Free energy F~ and its gradient dF~/dH on H's block pattern (paper:
+ * Analytical free-energy derivatives, polynomial form; the interval is held
+ * fixed, so dF/dH = 2/(e_max - e_min) dF/dH_hat).  The forward pass keeps
+ * checkpoints every ceil(sqrt(p - 1)) steps and the backward pass replays one
+ * segment at a time, so memory grows with sqrt(p) vectors, not p.
+ *   NEF_out   [3]  N, E, F of the forward pass (nullable)
+ *   dFdH_out  [nnzb][bd][bd]  raw gradient G (nullable)
+ * The gradient also stays on the device for rfo_hf_forces. */
+int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
+                        double *NEF_out, double *dFdH_out);
+
+/* Hellmann-Feynman forces from the last gradient (paper: Observable
+ * response with S = I): for a two-centre model with
+ * dHdR [nnzb][3][bd][bd] = d H_IJ / d R_I for every stored block (host or
+ * device memory), force_a = -(sum_J <G_aJ, D_aJ> - sum_I <G_Ia, D_Ia>).
+ *   forces_out [n_block_rows][3].
+ * Errors: RFO_E_STATE before rfo_energy_and_dEdH. */
+int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out);
+
+/* Instrumentation: when enabled, the library records HIP events around each
+ * run of consecutive Chebyshev-step launches on its stream.  rfo_step_timing
+ * returns the mean step-kernel time (ms) over the steps recorded since the
+ * last reset, and their count. */
+int rfo_set_timing(rfo_ctx *ctx, int enabled);
+int rfo_step_timing(rfo_ctx *ctx, double *mean_ms, int64_t *n_steps);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RFO_H */

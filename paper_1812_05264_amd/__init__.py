@@ -1,0 +1,9 @@
+"""Randomized Chebyshev Fermi-operator expansion on MI355X (gfx950).
+
+The compute path is the HIP library librfo.so (include/rfo.h); this package holds
+its ctypes binding and a torch.autograd.Function around the free-energy gradient.
+"""
+
+from ._rfo import Engine, RfoError, library_path, load, PRECISIONS  # noqa: F401
+
+__all__ = ["Engine", "RfoError", "library_path", "load", "PRECISIONS"]

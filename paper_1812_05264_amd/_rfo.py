@@ -1,0 +1,208 @@
+"""ctypes binding of librfo.so (argument marshalling only).
+
+Each method of Engine forwards to the C entry point of the same name declared in
+include/rfo.h; all arithmetic runs in the library's HIP kernels.  PyTorch is
+imported first so that the library binds to the HIP runtime PyTorch loaded, and
+torch tensors (host or device) can be passed wherever the ABI takes a pointer.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library will share)
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfo.so")
+
+RFO_OK = 0
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+STATUS = {0: "RFO_OK", -1: "RFO_E_INVALID", -2: "RFO_E_STATE", -3: "RFO_E_NOMEM",
+          -4: "RFO_E_DEVICE", -5: "RFO_E_NUMERIC", -6: "RFO_E_UNSUPPORTED"}
+
+_lib = None
+
+
+class RfoError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{STATUS.get(code, code)}: {message}")
+        self.code = code
+        self.status = STATUS.get(code, str(code))
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Loads librfo.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with python -m paper_1812_05264_amd.build")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, dbl, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    lib.rfo_create.argtypes = [ctypes.POINTER(vp), i32, vp]
+    lib.rfo_destroy.argtypes = [vp]
+    lib.rfo_destroy.restype = None
+    lib.rfo_last_error.argtypes = [vp]
+    lib.rfo_last_error.restype = ctypes.c_char_p
+    lib.rfo_set_hamiltonian.argtypes = [vp, i64, i32, vp, vp, vp, dbl, dbl, i32]
+    lib.rfo_get_interval.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.rfo_set_probes.argtypes = [vp, i64, vp, vp]
+    lib.rfo_fermi_moments.argtypes = [vp, dbl, dbl, i64, vp, vp, vp]
+    lib.rfo_energy_and_dEdH.argtypes = [vp, dbl, dbl, i64, vp, vp]
+    lib.rfo_hf_forces.argtypes = [vp, vp, vp]
+    lib.rfo_set_timing.argtypes = [vp, i32]
+    lib.rfo_step_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    for f in ("rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
+              "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing",
+              "rfo_step_timing"):
+        getattr(lib, f).restype = i32
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    """Address of a contiguous numpy array or torch tensor (None -> NULL)."""
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr()
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return a.ctypes.data
+
+
+def _host(a, dtype):
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Engine:
+    """One library context on one GPU, issuing work on one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = load()
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream(device)
+        handle = stream.cuda_stream if isinstance(stream, torch.cuda.Stream) else stream
+        ctx = ctypes.c_void_p()
+        rc = self._lib.rfo_create(ctypes.byref(ctx), int(device), handle)
+        if rc != RFO_OK:
+            raise RfoError(rc, self._lib.rfo_last_error(None).decode())
+        self._ctx = ctx
+        self.device = device
+        self.n_block_rows = 0
+        self.block_dim = 0
+        self.nnzb = 0
+        self.n_probes = 0
+        self.precision = "fp64"
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.rfo_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != RFO_OK:
+            raise RfoError(rc, self._lib.rfo_last_error(self._ctx).decode())
+
+    # -- rfo_set_hamiltonian ------------------------------------------------------
+    def set_hamiltonian(self, row_ptr, col_idx, values, block_dim, e_min=0.0, e_max=0.0,
+                        precision="fp64"):
+        """row_ptr/col_idx: host arrays (None, None keeps the pattern); values: FP64
+        [nnzb, bd, bd] numpy array or torch tensor (host or device).  e_min >= e_max
+        asks for the widened Gershgorin interval."""
+        if row_ptr is None and col_idx is None:
+            rp = ci = None
+            nb = self.n_block_rows
+        else:
+            rp = _host(row_ptr, np.int64)
+            ci = _host(col_idx, np.int32)
+            nb = rp.shape[0] - 1
+        if isinstance(values, torch.Tensor):
+            if values.dtype != torch.float64:
+                raise TypeError("values must be float64")
+            vals = values.contiguous()
+        else:
+            vals = np.ascontiguousarray(values, dtype=np.float64)
+        self._keep = (rp, ci, vals)
+        self._check(self._lib.rfo_set_hamiltonian(self._ctx, nb, int(block_dim), _ptr(rp), _ptr(ci),
+                                                  _ptr(vals), float(e_min), float(e_max),
+                                                  PRECISIONS[precision]))
+        self._keep = None
+        self.n_block_rows = nb
+        self.block_dim = int(block_dim)
+        self.nnzb = int(vals.shape[0]) if ci is None else int(ci.shape[0])
+        self.precision = precision
+        return self.interval()
+
+    def set_values(self, values):
+        """Replaces the values, keeping pattern, interval and precision."""
+        a, b = self.interval()
+        return self.set_hamiltonian(None, None, values, self.block_dim, a, b, self.precision)
+
+    def interval(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.rfo_get_interval(self._ctx, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    # -- rfo_set_probes -------------------------------------------------------------
+    def set_probes(self, R, weights=None):
+        R = _host(R, np.float64)
+        w = None if weights is None else _host(weights, np.float64)
+        self._check(self._lib.rfo_set_probes(self._ctx, int(R.shape[1]), _ptr(R), _ptr(w)))
+        self.n_probes = int(R.shape[1])
+
+    # -- rfo_fermi_moments ----------------------------------------------------------
+    def fermi_moments(self, T, mu, n_terms, moments=True, density=False, density_out=None):
+        """Returns dict(N, E, F, moments [s, p] or None, density [nnzb, bd, bd] or None).
+        density_out may be a preallocated FP64 torch tensor (host or device)."""
+        mom = np.empty((self.n_probes, int(n_terms))) if moments else None
+        nef = np.empty(3)
+        dens = density_out
+        if density and dens is None:
+            dens = np.empty((self.nnzb, self.block_dim, self.block_dim))
+        self._check(self._lib.rfo_fermi_moments(self._ctx, float(T), float(mu), int(n_terms),
+                                                _ptr(mom), _ptr(nef), _ptr(dens)))
+        return {"N": float(nef[0]), "E": float(nef[1]), "F": float(nef[2]), "moments": mom,
+                "density": dens}
+
+    # -- rfo_energy_and_dEdH --------------------------------------------------------
+    def energy_and_dEdH(self, T, mu, n_terms, gradient=True, dFdH_out=None):
+        nef = np.empty(3)
+        g = dFdH_out
+        if gradient and g is None:
+            g = np.empty((self.nnzb, self.block_dim, self.block_dim))
+        self._check(self._lib.rfo_energy_and_dEdH(self._ctx, float(T), float(mu), int(n_terms),
+                                                  _ptr(nef), _ptr(g)))
+        return {"N": float(nef[0]), "E": float(nef[1]), "F": float(nef[2]), "dFdH": g}
+
+    # -- rfo_hf_forces --------------------------------------------------------------
+    def hf_forces(self, dHdR):
+        if isinstance(dHdR, torch.Tensor):
+            d = dHdR.contiguous()
+        else:
+            d = np.ascontiguousarray(dHdR, dtype=np.float64)
+        out = np.empty((self.n_block_rows, 3))
+        self._check(self._lib.rfo_hf_forces(self._ctx, _ptr(d), _ptr(out)))
+        return out
+
+    # -- instrumentation --------------------------------------------------------------
+    def set_timing(self, enabled=True):
+        self._check(self._lib.rfo_set_timing(self._ctx, 1 if enabled else 0))
+
+    def step_timing(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self._check(self._lib.rfo_step_timing(self._ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

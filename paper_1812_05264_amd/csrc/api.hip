@@ -1,0 +1,779 @@
+// C ABI of the randomized Fermi-operator library: validation, device buffers and
+// the orchestration of the kernels (see include/rfo.h for the contract).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rfo.h"
+#include "rfo_internal.h"
+
+namespace {
+
+std::string g_create_error;
+
+struct DevBuf {
+  void *p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct rfo_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // Hamiltonian
+  bool has_h = false;
+  int64_t nb = 0, n = 0, nnzb = 0;
+  int bd = 0, prec = 0;
+  double e_min = 0.0, e_max = 0.0;
+  std::vector<int64_t> row_ptr_h;
+  std::vector<int32_t> col_h;
+  DevBuf row_ptr, col, brow, tpos, hraw, h64, h32, hbf16, gscratch;
+
+  // probes
+  bool has_r = false;
+  int64_t s = 0;
+  int sp = 0;
+  bool signs = false;
+  DevBuf sgn, rden, w;
+
+  // work buffers
+  DevBuf vec, acc, ring, moments, coef, samples, costab, small, flags, G, dHdR, forces;
+  bool has_grad = false;
+
+  // instrumentation
+  bool timing = false;
+  double t_ms = 0.0;
+  int64_t t_steps = 0;
+  std::vector<hipEvent_t> events;
+  int *flags_h = nullptr;
+
+  ~rfo_ctx() {
+    hipSetDevice(device);
+    DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch,
+                     &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
+                     &costab, &small, &flags, &G, &dHdR, &forces};
+    for (DevBuf *b : all)
+      if (b->p) hipFree(b->p);
+    for (hipEvent_t e : events) hipEventDestroy(e);
+    if (flags_h) hipHostFree(flags_h);
+  }
+};
+
+namespace {
+
+int fail(rfo_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(ctx, RFO_E_DEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                  __FILE__, __LINE__);                                                   \
+  } while (0)
+
+#define TRY(expr)             \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ != RFO_OK) return r_; \
+  } while (0)
+
+int ensure(rfo_ctx *ctx, DevBuf &b, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  if (b.bytes >= bytes) return RFO_OK;
+  if (b.p) {
+    hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(ctx, RFO_E_NOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return RFO_OK;
+}
+
+void release(DevBuf &b) {
+  if (b.p) hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+template <typename T>
+T *P(DevBuf &b) {
+  return static_cast<T *>(b.p);
+}
+
+// Launch decomposition of the Chebyshev step for the current H, probes and precision.
+struct Plan {
+  int vt_bytes;    // bytes per vector element
+  int ppl;         // probes per lane
+  int n_pt;        // probe tiles
+  int rows_per_wg; // block rows per workgroup
+  int n_rg;        // row groups
+  int ring;        // moment ring depth
+  size_t vec_elems;
+};
+
+Plan make_plan(const rfo_ctx *c) {
+  Plan pl;
+  pl.vt_bytes = c->prec == RFO_FP64 ? 8 : 4;
+  const int max_ppl = 16 / pl.vt_bytes;
+  pl.ppl = 1;
+  for (int q = max_ppl; q >= 1; q >>= 1)
+    if (c->sp % (64 * q) == 0) {
+      pl.ppl = q;
+      break;
+    }
+  pl.n_pt = c->sp / (64 * pl.ppl);
+  const int64_t target_wgs = 2048;
+  int64_t rows = (c->nb * pl.n_pt + target_wgs - 1) / target_wgs;
+  rows = std::max<int64_t>(rows, rfo::kWaves);
+  rows = (rows + rfo::kWaves - 1) / rfo::kWaves * rfo::kWaves;
+  if (const char *env = getenv("RFO_ROWS_PER_WG")) {
+    const int64_t r = atoll(env);
+    if (r >= 1) rows = r;
+  }
+  pl.rows_per_wg = (int)rows;
+  pl.n_rg = (int)((c->nb + rows - 1) / rows);
+  pl.ring = 32;
+  pl.vec_elems = (size_t)c->n * (size_t)c->sp;
+  return pl;
+}
+
+void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
+  memset(&a, 0, sizeof(a));
+  a.row_ptr = P<int64_t>(c->row_ptr);
+  a.col = P<int32_t>(c->col);
+  a.hval = c->prec == RFO_FP64 ? c->h64.p : c->h32.p;
+  a.sgn = c->signs ? P<uint64_t>(c->sgn) : nullptr;
+  a.rden = c->signs ? nullptr : P<double>(c->rden);
+  a.nb = c->nb;
+  a.sp = c->sp;
+  a.rows_per_wg = pl.rows_per_wg;
+  a.n_rg = pl.n_rg;
+  a.n_pt = pl.n_pt;
+}
+
+void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
+  memset(&a, 0, sizeof(a));
+  a.sgn = c->signs ? P<uint64_t>(c->sgn) : nullptr;
+  a.rden = c->signs ? nullptr : P<double>(c->rden);
+  a.nb = c->nb;
+  a.bd = c->bd;
+  a.sp = c->sp;
+  a.rows_per_wg = pl.rows_per_wg;
+  a.n_rg = pl.n_rg;
+  a.n_pt = pl.n_pt;
+  a.ppl = pl.ppl;
+}
+
+int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 : 1; }
+
+char *vec_at(rfo_ctx *c, const Plan &pl, DevBuf &b, int64_t i) {
+  return static_cast<char *>(b.p) + (size_t)i * pl.vec_elems * pl.vt_bytes;
+}
+
+hipEvent_t next_event(rfo_ctx *c, size_t idx) {
+  while (c->events.size() <= idx) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->events.push_back(e);
+  }
+  return c->events[idx];
+}
+
+int copy_out(rfo_ctx *ctx, void *dst, const void *src, size_t bytes) {
+  if (!dst || bytes == 0) return RFO_OK;
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, ctx->stream));
+  return RFO_OK;
+}
+
+int check_flags_and_finish(rfo_ctx *ctx, size_t n_events) {
+  HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (ctx->timing) {
+    for (size_t i = 0; i + 1 < n_events; i += 2) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ctx->events[i], ctx->events[i + 1]));
+      ctx->t_ms += ms;
+    }
+  }
+  const int f = *ctx->flags_h;
+  if (f & 4)
+    return fail(ctx, RFO_E_NUMERIC,
+                "a Chebyshev moment exceeded ||r||^2 or is not finite: the spectrum is not "
+                "inside [e_min, e_max] = [%g, %g]", ctx->e_min, ctx->e_max);
+  return RFO_OK;
+}
+
+// Forward recurrence over n_terms terms with moments (and optionally the density
+// accumulator and checkpoints).  Vectors live in `bufs` (first two slots used as
+// the rolling pair).  On return *last/*before hold the pointers of y_{p-1}, y_{p-2}.
+struct Checkpoints {
+  int64_t m = 0, Q = 0;
+  DevBuf *store = nullptr;  // 2 (Q - 1) vectors: [q-1][0] = y_{qm-1}, [q-1][1] = y_{qm}
+};
+
+int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_acc,
+                const Checkpoints *ck, size_t *n_events) {
+  const int kp = kernel_precision(ctx);
+  const double tol = ctx->prec == RFO_FP64 ? 1e-6 : 1e-3;
+  const size_t slot = (size_t)pl.n_rg * ctx->sp;
+  double *ring = P<double>(ctx->ring);
+  double *mom = P<double>(ctx->moments);
+  double *coef = P<double>(ctx->coef);
+  int *flags = P<int>(ctx->flags);
+  char *A = vec_at(ctx, pl, bufs, 0);
+  char *B = vec_at(ctx, pl, bufs, 1);
+  void *accp = use_acc ? ctx->acc.p : nullptr;
+
+  auto save = [&](int64_t k, const void *src) -> int {
+    if (!ck || ck->Q < 2) return RFO_OK;
+    const int64_t m = ck->m;
+    for (int64_t q = 1; q < ck->Q; ++q) {
+      int which = -1;
+      if (k == q * m - 1) which = 0;
+      if (k == q * m) which = 1;
+      if (which >= 0) {
+        char *dst = vec_at(ctx, pl, *ck->store, 2 * (q - 1) + which);
+        HIPCHK(hipMemcpyAsync(dst, src, pl.vec_elems * pl.vt_bytes, hipMemcpyDeviceToDevice,
+                              ctx->stream));
+      }
+    }
+    return RFO_OK;
+  };
+
+  rfo::InitArgs ia;
+  fill_init(ctx, pl, ia);
+  ia.out = A;
+  ia.scale = nullptr;
+  ia.acc = accp;
+  ia.alpha = coef;  // alpha^f_0
+  ia.part = ring;
+  HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+  HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, 0, 1, pl.n_rg, ctx->sp, mom, 0, tol, flags,
+                                   ctx->stream));
+  TRY(save(0, A));
+
+  rfo::StepArgs sa;
+  fill_step(ctx, pl, sa);
+  char *cur = A, *prev = B;
+  int64_t batch_start = 1;
+  size_t ev = 0;
+  for (int64_t k = 0; k + 1 < p; ++k) {
+    if (ctx->timing && k + 1 == batch_start) {
+      hipEvent_t e = next_event(ctx, ev++);
+      if (!e) return fail(ctx, RFO_E_DEVICE, "hipEventCreate failed");
+      HIPCHK(hipEventRecord(e, ctx->stream));
+    }
+    char *out = (k == 0) ? B : prev;
+    sa.x = cur;
+    sa.prev = prev;
+    sa.out = out;
+    sa.c1 = (k == 0) ? 1.0 : 2.0;
+    sa.c2 = (k == 0) ? 0.0 : -1.0;
+    sa.beta = nullptr;
+    sa.acc = accp;
+    sa.alpha = coef + (k + 1);
+    sa.part = ring + (size_t)((k + 1) % pl.ring) * slot;
+    HIPCHK(rfo::launch_step(ctx->bd, kp, pl.ppl, sa, ctx->stream));
+    prev = cur;
+    cur = out;
+    const int64_t idx = k + 1;
+    const bool flush = (idx - batch_start + 1 == pl.ring) || (idx == p - 1);
+    if (flush) {
+      if (ctx->timing) {
+        hipEvent_t e = next_event(ctx, ev++);
+        if (!e) return fail(ctx, RFO_E_DEVICE, "hipEventCreate failed");
+        HIPCHK(hipEventRecord(e, ctx->stream));
+        ctx->t_steps += idx - batch_start + 1;
+      }
+      HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, batch_start, (int)(idx - batch_start + 1),
+                                       pl.n_rg, ctx->sp, mom, 1, tol, flags, ctx->stream));
+      batch_start = idx + 1;
+    }
+    TRY(save(idx, cur));
+  }
+  *n_events = ev;
+  return RFO_OK;
+}
+
+int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) {
+  if (!ctx) return RFO_E_INVALID;
+  if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "no Hamiltonian: call rfo_set_hamiltonian first");
+  if (!ctx->has_r) return fail(ctx, RFO_E_STATE, "no probes: call rfo_set_probes first");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(ctx, RFO_E_INVALID, "T must be finite and > 0");
+  if (!std::isfinite(mu)) return fail(ctx, RFO_E_INVALID, "mu must be finite");
+  if (p < 1 || p > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_terms must be in [1, 2^20]");
+  if (ctx->prec == RFO_BF16)
+    return fail(ctx, RFO_E_UNSUPPORTED, "BF16 steps are not available in this build");
+  HIPCHK(hipSetDevice(ctx->device));
+  pl = make_plan(ctx);
+  const int64_t nq = 4 * p;
+  TRY(ensure(ctx, ctx->ring, (size_t)pl.ring * pl.n_rg * ctx->sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->moments, (size_t)p * ctx->sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->coef, (size_t)3 * p * sizeof(double)));
+  TRY(ensure(ctx, ctx->samples, (size_t)3 * nq * sizeof(double)));
+  TRY(ensure(ctx, ctx->costab, (size_t)4 * nq * sizeof(double)));
+  TRY(ensure(ctx, ctx->small, 64 * sizeof(double)));
+  HIPCHK(hipMemsetAsync(ctx->flags.p, 0, sizeof(int), ctx->stream));
+  HIPCHK(rfo::launch_coefficients(ctx->e_min, ctx->e_max, T, mu, p, nq, P<double>(ctx->samples),
+                                  P<double>(ctx->costab), P<double>(ctx->coef), ctx->stream));
+  return RFO_OK;
+}
+
+int copy_moments_out(rfo_ctx *ctx, int64_t p, double *moments_out) {
+  if (!moments_out) return RFO_OK;
+  // internal [p][sp] -> caller [s][p]
+  std::vector<double> tmp((size_t)p * ctx->sp);
+  HIPCHK(hipMemcpyAsync(tmp.data(), ctx->moments.p, tmp.size() * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<double> outv((size_t)ctx->s * p);
+  for (int64_t c = 0; c < ctx->s; ++c)
+    for (int64_t k = 0; k < p; ++k) outv[(size_t)c * p + k] = tmp[(size_t)k * ctx->sp + c];
+  HIPCHK(hipMemcpy(moments_out, outv.data(), outv.size() * sizeof(double), hipMemcpyDefault));
+  return RFO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rfo_create(rfo_ctx **out, int device, void *hip_stream) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return RFO_E_INVALID;
+  }
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) {
+    g_create_error = std::string("no HIP device: ") + hipGetErrorString(e);
+    return RFO_E_DEVICE;
+  }
+  if (device < 0 || device >= count) {
+    g_create_error = "device index out of range";
+    return RFO_E_INVALID;
+  }
+  e = hipSetDevice(device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipSetDevice failed: ") + hipGetErrorString(e);
+    return RFO_E_DEVICE;
+  }
+  rfo_ctx *c = new rfo_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipHostMalloc(reinterpret_cast<void **>(&c->flags_h), sizeof(int)) != hipSuccess ||
+      ensure(c, c->flags, sizeof(int)) != RFO_OK) {
+    g_create_error = "allocation of the status flag failed";
+    delete c;
+    return RFO_E_NOMEM;
+  }
+  *out = c;
+  return RFO_OK;
+}
+
+void rfo_destroy(rfo_ctx *ctx) { delete ctx; }
+
+const char *rfo_last_error(const rfo_ctx *ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const int64_t *row_ptr,
+                        const int32_t *col_idx, const double *values, double e_min,
+                        double e_max, int precision) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (block_dim != 1 && block_dim != 9)
+    return fail(ctx, RFO_E_INVALID, "block_dim must be 1 or 9 (got %d)", block_dim);
+  if (n_block_rows < 1 || n_block_rows > ((int64_t)1 << 30))
+    return fail(ctx, RFO_E_INVALID, "n_block_rows out of range");
+  if (precision != RFO_FP64 && precision != RFO_FP32 && precision != RFO_BF16)
+    return fail(ctx, RFO_E_INVALID, "unknown precision %d", precision);
+  if (precision == RFO_BF16 && block_dim != 9)
+    return fail(ctx, RFO_E_UNSUPPORTED, "BF16 MFMA steps need 9x9 blocks");
+  if (!values) return fail(ctx, RFO_E_INVALID, "values is NULL");
+  if (!std::isfinite(e_min) || !std::isfinite(e_max))
+    return fail(ctx, RFO_E_INVALID, "e_min and e_max must be finite");
+  const bool keep_pattern = (row_ptr == nullptr && col_idx == nullptr);
+  if ((row_ptr == nullptr) != (col_idx == nullptr))
+    return fail(ctx, RFO_E_INVALID, "row_ptr and col_idx must both be given or both be NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+
+  if (keep_pattern) {
+    if (!ctx->has_h && ctx->row_ptr_h.empty())
+      return fail(ctx, RFO_E_STATE, "no previous pattern to keep");
+    if (n_block_rows != ctx->nb || block_dim != ctx->bd)
+      return fail(ctx, RFO_E_INVALID, "n_block_rows/block_dim differ from the kept pattern");
+  } else {
+    // ---- host validation of the pattern
+    const int64_t nb = n_block_rows;
+    if (row_ptr[0] != 0) return fail(ctx, RFO_E_INVALID, "row_ptr[0] must be 0");
+    for (int64_t i = 0; i < nb; ++i)
+      if (row_ptr[i + 1] < row_ptr[i]) return fail(ctx, RFO_E_INVALID, "row_ptr not monotone at %lld", (long long)i);
+    const int64_t nnzb = row_ptr[nb];
+    if (nnzb < nb || nnzb > ((int64_t)1 << 34)) return fail(ctx, RFO_E_INVALID, "bad nnzb %lld", (long long)nnzb);
+    std::vector<int64_t> tpos(nnzb), brow(nnzb);
+    for (int64_t I = 0; I < nb; ++I) {
+      bool diag = false;
+      for (int64_t z = row_ptr[I]; z < row_ptr[I + 1]; ++z) {
+        const int32_t J = col_idx[z];
+        if (J < 0 || J >= nb) return fail(ctx, RFO_E_INVALID, "col_idx out of range in row %lld", (long long)I);
+        if (z > row_ptr[I] && col_idx[z - 1] >= J)
+          return fail(ctx, RFO_E_INVALID, "col_idx not strictly increasing in row %lld", (long long)I);
+        if (J == I) diag = true;
+        brow[z] = I;
+      }
+      if (!diag) return fail(ctx, RFO_E_INVALID, "block row %lld has no diagonal block", (long long)I);
+    }
+    for (int64_t I = 0; I < nb; ++I) {
+      for (int64_t z = row_ptr[I]; z < row_ptr[I + 1]; ++z) {
+        const int32_t J = col_idx[z];
+        const int32_t *b0 = col_idx + row_ptr[J], *b1 = col_idx + row_ptr[J + 1];
+        const int32_t *hit = std::lower_bound(b0, b1, (int32_t)I);
+        if (hit == b1 || *hit != (int32_t)I)
+          return fail(ctx, RFO_E_INVALID, "pattern not symmetric: (%lld,%d) has no mirror",
+                      (long long)I, J);
+        tpos[z] = hit - col_idx;
+      }
+    }
+    const int64_t n = nb * block_dim;
+    if (ctx->has_r && n != ctx->n) {
+      ctx->has_r = false;
+      ctx->s = 0;
+    }
+    ctx->has_h = false;
+    ctx->has_grad = false;
+    ctx->nb = nb;
+    ctx->bd = block_dim;
+    ctx->n = n;
+    ctx->nnzb = nnzb;
+    ctx->row_ptr_h.assign(row_ptr, row_ptr + nb + 1);
+    ctx->col_h.assign(col_idx, col_idx + nnzb);
+    TRY(ensure(ctx, ctx->row_ptr, (nb + 1) * sizeof(int64_t)));
+    TRY(ensure(ctx, ctx->col, nnzb * sizeof(int32_t)));
+    TRY(ensure(ctx, ctx->brow, nnzb * sizeof(int64_t)));
+    TRY(ensure(ctx, ctx->tpos, nnzb * sizeof(int64_t)));
+    HIPCHK(hipMemcpyAsync(ctx->row_ptr.p, row_ptr, (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->col.p, col_idx, nnzb * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->brow.p, brow.data(), nnzb * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->tpos.p, tpos.data(), nnzb * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
+  }
+  ctx->has_h = false;
+  ctx->has_grad = false;
+  const size_t nval = (size_t)ctx->nnzb * ctx->bd * ctx->bd;
+  TRY(ensure(ctx, ctx->hraw, nval * sizeof(double)));
+  TRY(ensure(ctx, ctx->h64, nval * sizeof(double)));
+  if (precision == RFO_FP32) TRY(ensure(ctx, ctx->h32, nval * sizeof(float)));
+  HIPCHK(hipMemcpyAsync(ctx->hraw.p, values, nval * sizeof(double), hipMemcpyDefault, ctx->stream));
+
+  if (e_min >= e_max) {
+    const int nblk = (int)((ctx->n + rfo::kWG - 1) / rfo::kWG);
+    TRY(ensure(ctx, ctx->gscratch, (size_t)2 * nblk * sizeof(double)));
+    TRY(ensure(ctx, ctx->small, 64 * sizeof(double)));
+    HIPCHK(rfo::launch_gershgorin(P<double>(ctx->hraw), P<int64_t>(ctx->row_ptr), P<int32_t>(ctx->col),
+                                  ctx->nb, ctx->bd, P<double>(ctx->gscratch), P<double>(ctx->small),
+                                  ctx->stream));
+    double lohi[2];
+    HIPCHK(hipMemcpyAsync(lohi, ctx->small.p, sizeof(lohi), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (!std::isfinite(lohi[0]) || !std::isfinite(lohi[1]))
+      return fail(ctx, RFO_E_NUMERIC, "non-finite Hamiltonian values");
+    const double c = 0.5 * (lohi[0] + lohi[1]);
+    double h = 1.01 * 0.5 * (lohi[1] - lohi[0]);
+    h = std::max(h, 1e-12 * std::max(1.0, std::fabs(c)));
+    e_min = c - h;
+    e_max = c + h;
+  }
+  ctx->e_min = e_min;
+  ctx->e_max = e_max;
+  ctx->prec = precision;
+  HIPCHK(hipMemsetAsync(ctx->flags.p, 0, sizeof(int), ctx->stream));
+  HIPCHK(rfo::launch_map(P<double>(ctx->hraw), P<int64_t>(ctx->brow), P<int32_t>(ctx->col),
+                         P<int64_t>(ctx->tpos), ctx->nnzb, ctx->bd, e_min, e_max,
+                         P<double>(ctx->h64), precision == RFO_FP32 ? P<float>(ctx->h32) : nullptr,
+                         P<int>(ctx->flags), ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*ctx->flags_h & 1) return fail(ctx, RFO_E_NUMERIC, "non-finite Hamiltonian values");
+  if (*ctx->flags_h & 2) return fail(ctx, RFO_E_INVALID, "Hamiltonian values are not symmetric (H_JI != H_IJ^T)");
+  ctx->has_h = true;
+  return RFO_OK;
+}
+
+int rfo_get_interval(const rfo_ctx *ctx, double *e_min, double *e_max) {
+  if (!ctx || !e_min || !e_max) return RFO_E_INVALID;
+  if (!ctx->has_h) return RFO_E_STATE;
+  *e_min = ctx->e_min;
+  *e_max = ctx->e_max;
+  return RFO_OK;
+}
+
+int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R, const double *weights) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "set the Hamiltonian before the probes");
+  if (!R) return fail(ctx, RFO_E_INVALID, "R is NULL");
+  if (n_probes < 1 || n_probes > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_probes out of range");
+  if (weights)
+    for (int64_t c = 0; c < n_probes; ++c)
+      if (!std::isfinite(weights[c])) return fail(ctx, RFO_E_INVALID, "non-finite weight");
+  HIPCHK(hipSetDevice(ctx->device));
+  ctx->has_r = false;
+  ctx->has_grad = false;
+  const int sp = (int)((n_probes + 63) / 64 * 64);
+  const size_t n = (size_t)ctx->n;
+  TRY(ensure(ctx, ctx->rden, n * sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->sgn, n * (sp / 64) * sizeof(uint64_t)));
+  TRY(ensure(ctx, ctx->w, sp * sizeof(double)));
+  HIPCHK(hipMemsetAsync(ctx->rden.p, 0, n * sp * sizeof(double), ctx->stream));
+  HIPCHK(hipMemcpy2DAsync(ctx->rden.p, sp * sizeof(double), R, n_probes * sizeof(double),
+                          n_probes * sizeof(double), n, hipMemcpyHostToDevice, ctx->stream));
+  std::vector<double> w(sp, 0.0);
+  for (int64_t c = 0; c < n_probes; ++c) w[c] = weights ? weights[c] : 1.0 / (double)n_probes;
+  HIPCHK(hipMemcpyAsync(ctx->w.p, w.data(), sp * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->flags.p, 0, sizeof(int), ctx->stream));
+  HIPCHK(rfo::launch_probe_pack(P<double>(ctx->rden), (int64_t)n, (int)n_probes, sp,
+                                P<uint64_t>(ctx->sgn), P<int>(ctx->flags), ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*ctx->flags_h & 2) return fail(ctx, RFO_E_NUMERIC, "non-finite probe entries");
+  ctx->signs = (*ctx->flags_h & 1) == 0;
+  if (ctx->signs) release(ctx->rden);
+  ctx->s = n_probes;
+  ctx->sp = sp;
+  ctx->has_r = true;
+  return RFO_OK;
+}
+
+int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double *moments_out,
+                      double *NEF_out, double *density_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  Plan pl;
+  TRY(prepare_call(ctx, T, mu, n_terms, pl));
+  const bool dens = density_out != nullptr;
+  TRY(ensure(ctx, ctx->vec, 2 * pl.vec_elems * pl.vt_bytes));
+  if (dens) TRY(ensure(ctx, ctx->acc, pl.vec_elems * pl.vt_bytes));
+  size_t n_events = 0;
+  TRY(run_forward(ctx, pl, n_terms, ctx->vec, dens, nullptr, &n_events));
+  double *obs = P<double>(ctx->small);
+  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef),
+                            n_terms, ctx->sp, obs, ctx->stream));
+  if (dens) {
+    TRY(ensure(ctx, ctx->G, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
+    rfo::SddmmArgs a;
+    memset(&a, 0, sizeof(a));
+    a.brow = P<int64_t>(ctx->brow);
+    a.col = P<int32_t>(ctx->col);
+    a.nnzb = ctx->nnzb;
+    a.bd = ctx->bd;
+    a.sp = ctx->sp;
+    a.xbase = ctx->acc.p;
+    a.ybase = nullptr;
+    a.sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
+    a.rden = ctx->signs ? nullptr : P<double>(ctx->rden);
+    a.w = P<double>(ctx->w);
+    a.count = 1;
+    a.scale = 1.0;
+    a.first = 1.0;
+    a.rest = 1.0;
+    a.G = P<double>(ctx->G);
+    a.accumulate = 0;
+    HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
+    ctx->has_grad = false;  // G now holds the density
+    TRY(copy_out(ctx, density_out, ctx->G.p, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
+  }
+  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
+  TRY(check_flags_and_finish(ctx, n_events));
+  TRY(copy_moments_out(ctx, n_terms, moments_out));
+  return RFO_OK;
+}
+
+int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double *NEF_out,
+                        double *dFdH_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  Plan pl;
+  TRY(prepare_call(ctx, T, mu, n_terms, pl));
+  const int64_t p = n_terms;
+  const int kp = kernel_precision(ctx);
+  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
+  TRY(ensure(ctx, ctx->G, gbytes));
+  ctx->has_grad = false;
+  const int64_t P1 = p - 1;  // gradient terms use y_j, j = 0 .. p-2
+  int64_t m = 2;
+  while (m * m < P1) ++m;
+  const int64_t Q = P1 > 0 ? (P1 + m - 1) / m : 0;
+  // vector slots: ys [m] | zs [m + 2] | checkpoints [2 (Q - 1)]
+  const int64_t n_ys = m, n_zs = m + 2, n_ck = Q > 1 ? 2 * (Q - 1) : 0;
+  TRY(ensure(ctx, ctx->vec, (size_t)(n_ys + n_zs + n_ck) * pl.vec_elems * pl.vt_bytes));
+  const double *beta = P<double>(ctx->coef) + 2 * p;
+
+  // forward pass (rolling pair in ys[0], ys[1]) with checkpoints y_{qm-1}, y_{qm}
+  DevBuf ckview;
+  ckview.p = vec_at(ctx, pl, ctx->vec, n_ys + n_zs);
+  ckview.bytes = (size_t)n_ck * pl.vec_elems * pl.vt_bytes;
+  Checkpoints ck;
+  ck.m = m;
+  ck.Q = Q;
+  ck.store = &ckview;
+  size_t n_events = 0;
+  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, &n_events));
+  double *obs = P<double>(ctx->small);
+  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
+                            ctx->sp, obs, ctx->stream));
+
+  if (P1 == 0) {
+    HIPCHK(hipMemsetAsync(ctx->G.p, 0, gbytes, ctx->stream));
+  } else {
+    const size_t vb = pl.vec_elems * pl.vt_bytes;
+    auto ys = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, t); };
+    auto zs = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, n_ys + t); };
+    auto cka = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_ys + n_zs + 2 * (q - 1)); };
+    auto ckb = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_ys + n_zs + 2 * (q - 1) + 1); };
+    rfo::StepArgs sa;
+    fill_step(ctx, pl, sa);
+    rfo::InitArgs ia;
+    fill_init(ctx, pl, ia);
+    for (int64_t q = Q - 1; q >= 0; --q) {
+      const int64_t j0 = q * m, j1 = std::min(j0 + m, P1), len = j1 - j0;
+      // replay y_j, j in [j0, j1), into ys[0 .. len)
+      if (q == 0) {
+        ia.out = ys(0);
+        ia.scale = nullptr;
+        ia.acc = nullptr;
+        ia.part = nullptr;
+        HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+      } else {
+        HIPCHK(hipMemcpyAsync(ys(0), ckb(q), vb, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+      for (int64_t t = 1; t < len; ++t) {
+        sa.x = ys(t - 1);
+        if (t == 1) {
+          sa.prev = (j0 == 0) ? nullptr : cka(q);
+          sa.c1 = (j0 == 0) ? 1.0 : 2.0;
+          sa.c2 = (j0 == 0) ? 0.0 : -1.0;
+        } else {
+          sa.prev = ys(t - 2);
+          sa.c1 = 2.0;
+          sa.c2 = -1.0;
+        }
+        sa.out = ys(t);
+        sa.beta = nullptr;
+        sa.acc = nullptr;
+        sa.part = nullptr;
+        HIPCHK(rfo::launch_step(ctx->bd, kp, pl.ppl, sa, ctx->stream));
+      }
+      // reverse recurrence: zs[t] = z_{j0+1+t}; z_{p-1} = beta_{p-1} r,
+      // z_{p-2} = 2 H_hat z_{p-1} + beta_{p-2} r, z_i = 2 H_hat z_{i+1} - z_{i+2} + beta_i r
+      for (int64_t t = len - 1; t >= 0; --t) {
+        const int64_t i = j0 + 1 + t;
+        if (i == p - 1) {
+          ia.out = zs(t);
+          ia.scale = beta + (p - 1);
+          ia.acc = nullptr;
+          ia.part = nullptr;
+          HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+        } else {
+          sa.x = zs(t + 1);
+          sa.prev = (i == p - 2) ? nullptr : zs(t + 2);
+          sa.c1 = 2.0;
+          sa.c2 = (i == p - 2) ? 0.0 : -1.0;
+          sa.out = zs(t);
+          sa.beta = beta + i;
+          sa.acc = nullptr;
+          sa.part = nullptr;
+          HIPCHK(rfo::launch_step(ctx->bd, kp, pl.ppl, sa, ctx->stream));
+        }
+      }
+      // G += sum_{j in segment} c_j z_{j+1} y_j^T, c_0 = 1, c_j = 2; times 2/(e_max - e_min)
+      rfo::SddmmArgs a;
+      memset(&a, 0, sizeof(a));
+      a.brow = P<int64_t>(ctx->brow);
+      a.col = P<int32_t>(ctx->col);
+      a.nnzb = ctx->nnzb;
+      a.bd = ctx->bd;
+      a.sp = ctx->sp;
+      a.xbase = zs(0);
+      a.xstride = (int64_t)pl.vec_elems;
+      a.ybase = ys(0);
+      a.ystride = (int64_t)pl.vec_elems;
+      a.w = P<double>(ctx->w);
+      a.count = (int)len;
+      a.j0 = j0;
+      a.scale = 2.0 / (ctx->e_max - ctx->e_min);
+      a.first = 1.0;
+      a.rest = 2.0;
+      a.G = P<double>(ctx->G);
+      a.accumulate = (q == Q - 1) ? 0 : 1;
+      HIPCHK(rfo::launch_sddmm(kp, a, ctx->stream));
+      if (q > 0) {
+        // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}
+        HIPCHK(hipMemcpyAsync(zs(m), zs(0), vb, hipMemcpyDeviceToDevice, ctx->stream));
+        HIPCHK(hipMemcpyAsync(zs(m + 1), zs(1), vb, hipMemcpyDeviceToDevice, ctx->stream));
+      }
+    }
+  }
+  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
+  TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
+  TRY(check_flags_and_finish(ctx, n_events));
+  ctx->has_grad = true;
+  return RFO_OK;
+}
+
+int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_grad) return fail(ctx, RFO_E_STATE, "no gradient: call rfo_energy_and_dEdH first");
+  if (!dHdR || !forces_out) return fail(ctx, RFO_E_INVALID, "NULL argument");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t dbytes = (size_t)ctx->nnzb * 3 * ctx->bd * ctx->bd * sizeof(double);
+  TRY(ensure(ctx, ctx->dHdR, dbytes));
+  TRY(ensure(ctx, ctx->forces, (size_t)ctx->nb * 3 * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(ctx->dHdR.p, dHdR, dbytes, hipMemcpyDefault, ctx->stream));
+  HIPCHK(rfo::launch_forces(P<int64_t>(ctx->row_ptr), P<int64_t>(ctx->tpos), P<double>(ctx->G),
+                            P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces),
+                            ctx->stream));
+  TRY(copy_out(ctx, forces_out, ctx->forces.p, (size_t)ctx->nb * 3 * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_set_timing(rfo_ctx *ctx, int enabled) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->timing = enabled != 0;
+  ctx->t_ms = 0.0;
+  ctx->t_steps = 0;
+  return RFO_OK;
+}
+
+int rfo_step_timing(rfo_ctx *ctx, double *mean_ms, int64_t *n_steps) {
+  if (!ctx || !mean_ms || !n_steps) return RFO_E_INVALID;
+  *n_steps = ctx->t_steps;
+  *mean_ms = ctx->t_steps > 0 ? ctx->t_ms / (double)ctx->t_steps : 0.0;
+  return RFO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Device helpers shared by the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rfo {
+
+// Workgroups are dispatched round-robin over the 8 XCDs (hardware id b runs on
+// XCD b % 8).  Remap so that each XCD owns one contiguous range of logical ids:
+// neighbouring rows then share that XCD's L2.
+__device__ __forceinline__ int xcd_logical(int b, int nwg) {
+  const int per = nwg >> 3, rem = nwg & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+template <typename T, int N>
+struct alignas(sizeof(T) * N) VecN {
+  T v[N];
+};
+
+template <typename T, int N>
+__device__ __forceinline__ VecN<T, N> ldv(const T *p) {
+  return *reinterpret_cast<const VecN<T, N> *>(p);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void stv(T *p, const VecN<T, N> &v) {
+  *reinterpret_cast<VecN<T, N> *>(p) = v;
+}
+
+// Probe entry r[row][c]: sign bits (bit 1 = +1, bit 0 = -1) or dense FP64.
+__device__ __forceinline__ double probe_value(const uint64_t *sgn, const double *rden,
+                                              int64_t row, int sp, int c) {
+  if (sgn) {
+    const uint64_t w = sgn[row * (sp >> 6) + (c >> 6)];
+    return ((w >> (c & 63)) & 1ull) ? 1.0 : -1.0;
+  }
+  return rden[row * sp + c];
+}
+
+// Butterfly sum over the 64 lanes of a wave; every lane gets the total.  The
+// pairing order is fixed, so the result is deterministic.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+}  // namespace rfo

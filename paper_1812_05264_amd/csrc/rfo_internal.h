@@ -1,0 +1,121 @@
+// Internal declarations shared by the host orchestration (api.hip) and the
+// kernel translation units.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rfo {
+
+constexpr int kWG = 256;            // threads per workgroup (4 wave64)
+constexpr int kWaves = kWG / 64;
+
+// ---------------------------------------------------------------------------
+// Chebyshev step: out = c1 * H_hat x + c2 * prev + beta * r, fused with
+//   moment partials   part[rg][c] += r_c . out        (when mom != 0)
+//   density accumulator acc += alpha * out              (when acc != nullptr)
+// Vectors are [n][sp] row-major (n = nb * bd scalar rows, sp = padded probes).
+// The grid is n_rg * n_pt workgroups; a workgroup owns `rows_per_wg` block rows
+// of one probe tile of 64*ppl probes.
+// ---------------------------------------------------------------------------
+struct StepArgs {
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const void *hval;        // H_hat blocks in the matrix type
+  const void *x;           // y_k (gathered)
+  const void *prev;        // y_{k-1} (may alias out)
+  void *out;               // y_{k+1}
+  const uint64_t *sgn;     // [n][sp/64] sign bits (bit 1 = +1), or nullptr
+  const double *rden;      // [n][sp] dense probes, or nullptr
+  double c1, c2;
+  const double *beta;      // device scalar: adds beta * r when non-null
+  void *acc;               // density accumulator or nullptr
+  const double *alpha;     // device scalar used with acc
+  double *part;            // [n_rg][sp] moment partials (ring slot) or nullptr
+  int64_t nb;              // block rows
+  int sp;
+  int rows_per_wg;
+  int n_rg, n_pt;
+};
+
+// precision: 0 = fp64 (double vectors, double H), 1 = fp32 (float vectors, float H)
+hipError_t launch_step(int bd, int precision, int ppl, const StepArgs &a, hipStream_t s);
+
+// y = scale * r (+ acc = alpha * r, + part = r . y) with the step kernel's decomposition
+struct InitArgs {
+  void *out;
+  const uint64_t *sgn;
+  const double *rden;
+  const double *scale;     // device scalar, nullptr = 1
+  void *acc;
+  const double *alpha;     // device scalar used with acc
+  double *part;
+  int64_t nb;
+  int bd;
+  int sp;
+  int rows_per_wg;
+  int n_rg, n_pt;
+  int ppl;
+};
+hipError_t launch_init(int precision, const InitArgs &a, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+// Spectral map H_hat = (2H - (a+b)I)/(b-a) plus validity checks (finite values,
+// symmetric values via the transpose map); writes fp64 and (optionally) fp32.
+hipError_t launch_map(const double *h, const int64_t *brow, const int32_t *col,
+                      const int64_t *tpos, int64_t nnzb, int bd, double e_min,
+                      double e_max, double *hhat64, float *hhat32, int *flags,
+                      hipStream_t s);
+// Gershgorin interval: per-workgroup partial min/max, then a final reduction.
+hipError_t launch_gershgorin(const double *h, const int64_t *row_ptr,
+                             const int32_t *col, int64_t nb, int bd,
+                             double *scratch, double *out2, hipStream_t s);
+// Probe classification (all +-1?) and packing to sign bits.
+hipError_t launch_probe_pack(const double *rden, int64_t n, int s_real, int sp,
+                             uint64_t *sgn, int *flags, hipStream_t st);
+// Chebyshev coefficients of f, x f, g by Chebyshev-Gauss quadrature.
+hipError_t launch_coefficients(double e_min, double e_max, double T, double mu,
+                               int64_t p, int64_t nq, double *samples,
+                               double *costab, double *coef, hipStream_t s);
+// Fixed-order reduction of moment partials: moments[k][c] for k in
+// [k0, k0 + count), ring slot of index k is k % ring.  Flags a moment that
+// exceeds (1 + tol) * moments[0][c].
+hipError_t launch_moment_reduce(const double *part, int ring, int64_t k0,
+                                int count, int n_rg, int sp, double *moments,
+                                int check, double tol, int *flags, hipStream_t s);
+// N, E, F from moments and coefficients.
+hipError_t launch_traces(const double *moments, const double *w,
+                         const double *coef, int64_t p, int sp, double *out3,
+                         hipStream_t s);
+// Masked outer products on the block pattern:
+//   G[nz] (+)= sum_t coef_t sum_c w_c X_t[I-block][c] Y_t[J-block][c]
+// X_t = xbase + t*xstride (precision-typed), Y_t = ybase + t*ystride, or the
+// probes when ybase == nullptr.  coef_t = scale * (j0 + t == 0 ? first : rest).
+struct SddmmArgs {
+  const int64_t *brow;
+  const int32_t *col;
+  int64_t nnzb;
+  int bd;
+  int sp;
+  const void *xbase;
+  int64_t xstride;
+  const void *ybase;
+  int64_t ystride;
+  const uint64_t *sgn;
+  const double *rden;
+  const double *w;
+  int count;
+  int64_t j0;
+  double scale, first, rest;
+  double *G;
+  int accumulate;
+};
+hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s);
+// Hellmann-Feynman forces from G and d H_IJ / d R_I blocks.
+hipError_t launch_forces(const int64_t *row_ptr, const int64_t *tpos,
+                         const double *G, const double *D, int64_t nb, int bd,
+                         double *F, hipStream_t s);
+
+}  // namespace rfo

@@ -1,0 +1,139 @@
+"""GPU parity: the HIP path against the FP64 oracle on identical seeded inputs.
+
+Sizes span several workgroup row groups, several probe tiles and a ragged probe
+tail (probe counts that are not multiples of 64).  Bar: normwise relative error
+<= 1e-10 in FP64 for moments, N/E/F, density blocks and gradient blocks.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import closed_form as cf
+from oracle import estimator as est
+from oracle import forces as ofo
+from oracle import trunc
+from tests.gpu_common import TOL, banner, engine_or_skip, load_hamiltonian, rel
+from workloads import cu_cluster, identity_probes, rademacher, simple_cubic
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (builder, probes, T, mu, p)
+    "sc8_config": (lambda: simple_cubic(8), 64, 0.1, 0.0, 256),
+    "sc12_ragged": (lambda: simple_cubic(12, disorder=0.8, config_id=21), 200, 0.1, 0.2, 300),
+    "cu55_ragged": (lambda: cu_cluster(55, config_id=22).bsr(), 100, 0.3, 0.5, 200),
+    "cu201": (lambda: cu_cluster(201, config_id=23).bsr(), 128, 0.2, 0.1, 160),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_fermi_moments_match_oracle(name):
+    build, s, T, mu, p = CASES[name]
+    banner(f"fermi_moments parity {name}")
+    eng = engine_or_skip()
+    H = build()
+    R = rademacher(H.n, s, config_id=500)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    g = eng.fermi_moments(T, mu, p, moments=True, density=True)
+    o = est.estimate(H, R, T, mu, p, density=True)
+    assert rel(g["moments"], o["moments"]) < TOL
+    for key in ("N", "E", "F"):
+        assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
+    assert rel(g["density"], o["density"]) < TOL
+
+
+def test_config_sc8_against_closed_form():
+    # the simple-cubic config: estimate within ~5 sigma of the exact band, trace identities exact
+    banner("sc8 closed form")
+    eng = engine_or_skip()
+    H = simple_cubic(8)
+    R = rademacher(512, 64, config_id=0)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    g = eng.fermi_moments(0.1, 0.0, 256, moments=True, density=True)
+    assert np.all(g["moments"][:, 0] == 512.0)
+    cl = cf.observables(8, -1.0, 0.1, 0.0)
+    P = trunc.observables(H.to_dense(), H.e_min, H.e_max, 0.1, 0.0, 256)["P"]
+    sigma = np.sqrt(2.0 * (np.sum(P ** 2) - np.sum(np.diag(P) ** 2)) / 64)
+    assert abs(g["N"] - cl["N"]) < 5 * sigma
+    diag = g["density"][H.block_rows() == H.col_idx, 0, 0]
+    assert abs(diag.mean() - 1.0) < 5 * sigma / 512
+
+
+def test_identity_probes_dense_mode_give_exact_traces():
+    banner("identity probes")
+    eng = engine_or_skip()
+    H = simple_cubic(4, disorder=0.6, config_id=24)
+    load_hamiltonian(eng, H)
+    eng.set_probes(identity_probes(H.n), weights=np.ones(H.n))
+    T, mu, p = 0.2, 0.1, 128
+    g = eng.fermi_moments(T, mu, p, moments=True, density=True)
+    tr = trunc.observables(H.to_dense(), H.e_min, H.e_max, T, mu, p)
+    for key in ("N", "E", "F"):
+        assert abs(g[key] - tr[key]) < 1e-11 * max(1.0, abs(tr[key]))
+    exact = trunc.exact_moments(H.to_dense(), H.e_min, H.e_max, p)
+    assert np.max(np.abs(g["moments"].sum(axis=0) - exact)) < 1e-10
+    rows, cols = H.block_rows(), H.col_idx
+    assert np.max(np.abs(g["density"][:, 0, 0] - tr["P"][rows, cols])) < 1e-12
+
+
+GRAD_CASES = {
+    "sc8_grad": (lambda: simple_cubic(8, disorder=0.5, config_id=25), 10, 0.15, 0.1, 97),
+    "cu55_grad": (lambda: cu_cluster(55, config_id=26), 7, 0.3, 0.4, 64),
+    "cu55_p2": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 2),
+    "cu55_p3": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 3),
+}
+
+
+@pytest.mark.parametrize("name", list(GRAD_CASES))
+def test_gradient_matches_oracle(name):
+    build, s, T, mu, p = GRAD_CASES[name]
+    banner(f"gradient parity {name}")
+    eng = engine_or_skip()
+    obj = build()
+    H = obj.bsr() if hasattr(obj, "bsr") else obj
+    R = rademacher(H.n, s, config_id=501)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    g = eng.energy_and_dEdH(T, mu, p)
+    o = est.estimate(H, R, T, mu, p, gradient=True)
+    assert abs(g["F"] - o["F"]) <= TOL * max(1.0, abs(o["F"]))
+    assert rel(g["dFdH"], o["dFdH"]) < TOL
+    if hasattr(obj, "dH_dR"):
+        D = obj.dH_dR()
+        fg = eng.hf_forces(D)
+        fo = ofo.hf_forces(H, o["dFdH"], D)
+        assert rel(fg, fo) < TOL
+        assert np.max(np.abs(fg.sum(axis=0))) < 1e-10 * np.max(np.abs(fg))
+
+
+def test_gradient_symmetric_and_deterministic():
+    banner("gradient symmetry and determinism")
+    eng = engine_or_skip()
+    H = cu_cluster(201, config_id=27).bsr()
+    R = rademacher(H.n, 64, config_id=502)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    g1 = eng.energy_and_dEdH(0.2, 0.1, 150)
+    g2 = eng.energy_and_dEdH(0.2, 0.1, 150)
+    assert np.array_equal(g1["dFdH"], g2["dFdH"]) and g1["F"] == g2["F"]
+    G = g1["dFdH"]
+    rows, cols = H.block_rows(), H.col_idx.astype(np.int64)
+    pos = {(int(r), int(c)): z for z, (r, c) in enumerate(zip(rows, cols))}
+    t = np.array([pos[(int(c), int(r))] for r, c in zip(rows, cols)])
+    assert rel(np.transpose(G[t], (0, 2, 1)), G) < 1e-11
+
+
+def test_moments_bitwise_deterministic():
+    banner("moments determinism")
+    eng = engine_or_skip()
+    H = simple_cubic(12, disorder=0.8, config_id=21)
+    R = rademacher(H.n, 200, config_id=500)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    a = eng.fermi_moments(0.1, 0.2, 300, density=True)
+    b = eng.fermi_moments(0.1, 0.2, 300, density=True)
+    assert np.array_equal(a["moments"], b["moments"])
+    assert np.array_equal(a["density"], b["density"])
+    assert a["N"] == b["N"] and a["E"] == b["E"] and a["F"] == b["F"]
