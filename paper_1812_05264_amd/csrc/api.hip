@@ -25,6 +25,7 @@ struct DevBuf {
 
 struct rfo_ctx {
   int device = 0;
+  int cus = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -130,24 +131,29 @@ struct Plan {
   int rows_per_wg; // block rows per workgroup
   int n_rg;        // row groups
   int ring;        // moment ring depth
+  int nt;          // non-temporal hints on streamed arrays
+  int rpi;         // rows per wave iteration
+  int grid;        // resident workgroups of the step kernels
   size_t vec_elems;
 };
 
 Plan make_plan(const rfo_ctx *c) {
   Plan pl;
   pl.vt_bytes = c->prec == RFO_FP64 ? 8 : 4;
-  const int max_ppl = 16 / pl.vt_bytes;
+  // 16 bytes per lane (FP64) or 16 (FP32, 9x9: 32 measured best) per gather
+  int want = 16 / pl.vt_bytes;
+  if (c->bd == 9 && c->prec != RFO_FP64) want = 4;
+  if (const char *env = getenv("RFO_PPL")) want = atoi(env);
   pl.ppl = 1;
-  for (int q = max_ppl; q >= 1; q >>= 1)
-    if (c->sp % (64 * q) == 0) {
+  for (int q = 4; q >= 1; q >>= 1)
+    if (q <= want && c->sp % (64 * q) == 0) {
       pl.ppl = q;
       break;
     }
   pl.n_pt = c->sp / (64 * pl.ppl);
-  const int64_t target_wgs = 2048;
-  int64_t rows = (c->nb * pl.n_pt + target_wgs - 1) / target_wgs;
-  rows = std::max<int64_t>(rows, rfo::kWaves);
-  rows = (rows + rfo::kWaves - 1) / rfo::kWaves * rfo::kWaves;
+  // rows per workgroup: small enough that the resident workgroups of an XCD
+  // cover a narrow band of rows, large enough to keep the moment partials small
+  int64_t rows = c->bd == 1 ? 8 : 4;
   if (const char *env = getenv("RFO_ROWS_PER_WG")) {
     const int64_t r = atoll(env);
     if (r >= 1) rows = r;
@@ -155,6 +161,20 @@ Plan make_plan(const rfo_ctx *c) {
   pl.rows_per_wg = (int)rows;
   pl.n_rg = (int)((c->nb + rows - 1) / rows);
   pl.ring = 32;
+  pl.nt = 1;
+  if (const char *env = getenv("RFO_NT")) pl.nt = atoi(env);
+  // 1x1 blocks: rows per wave iteration; 9x9 blocks: blocks per gather chunk
+  pl.rpi = c->bd == 1 ? 1 : 2;
+  if (const char *env = getenv("RFO_RPI")) pl.rpi = atoi(env);
+  // one resident wave of workgroups, a multiple of 8 (one share per XCD)
+  const int occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl,
+                                                       pl.rpi, pl.nt));
+  int64_t grid = (int64_t)c->cus * occ;
+  if (const char *env = getenv("RFO_GRID")) grid = std::max<int64_t>(8, atoll(env));
+  const int64_t units = (int64_t)pl.n_pt * pl.n_rg;
+  grid = std::min(grid, (units + 7) / 8 * 8);
+  grid = std::max<int64_t>(8, grid / 8 * 8);
+  pl.grid = (int)grid;
   pl.vec_elems = (size_t)c->n * (size_t)c->sp;
   return pl;
 }
@@ -171,6 +191,9 @@ void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
   a.rows_per_wg = pl.rows_per_wg;
   a.n_rg = pl.n_rg;
   a.n_pt = pl.n_pt;
+  a.nt = pl.nt;
+  a.rpi = pl.rpi;
+  a.grid = pl.grid;
 }
 
 void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
@@ -184,6 +207,7 @@ void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
   a.n_rg = pl.n_rg;
   a.n_pt = pl.n_pt;
   a.ppl = pl.ppl;
+  a.grid = pl.grid;
 }
 
 int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 : 1; }
@@ -237,7 +261,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
                 const Checkpoints *ck, size_t *n_events) {
   const int kp = kernel_precision(ctx);
   const double tol = ctx->prec == RFO_FP64 ? 1e-6 : 1e-3;
-  const size_t slot = (size_t)pl.n_rg * ctx->sp;
+  const size_t slot = (size_t)pl.grid * ctx->sp;
   double *ring = P<double>(ctx->ring);
   double *mom = P<double>(ctx->moments);
   double *coef = P<double>(ctx->coef);
@@ -270,7 +294,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
   ia.alpha = coef;  // alpha^f_0
   ia.part = ring;
   HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
-  HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, 0, 1, pl.n_rg, ctx->sp, mom, 0, tol, flags,
+  HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, 0, 1, pl.grid, ctx->sp, mom, 0, tol, flags,
                                    ctx->stream));
   TRY(save(0, A));
 
@@ -308,7 +332,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
         ctx->t_steps += idx - batch_start + 1;
       }
       HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, batch_start, (int)(idx - batch_start + 1),
-                                       pl.n_rg, ctx->sp, mom, 1, tol, flags, ctx->stream));
+                                       pl.grid, ctx->sp, mom, 1, tol, flags, ctx->stream));
       batch_start = idx + 1;
     }
     TRY(save(idx, cur));
@@ -329,7 +353,7 @@ int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) {
   HIPCHK(hipSetDevice(ctx->device));
   pl = make_plan(ctx);
   const int64_t nq = 4 * p;
-  TRY(ensure(ctx, ctx->ring, (size_t)pl.ring * pl.n_rg * ctx->sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->ring, (size_t)pl.ring * pl.grid * ctx->sp * sizeof(double)));
   TRY(ensure(ctx, ctx->moments, (size_t)p * ctx->sp * sizeof(double)));
   TRY(ensure(ctx, ctx->coef, (size_t)3 * p * sizeof(double)));
   TRY(ensure(ctx, ctx->samples, (size_t)3 * nq * sizeof(double)));
@@ -382,6 +406,10 @@ int rfo_create(rfo_ctx **out, int device, void *hip_stream) {
   }
   rfo_ctx *c = new rfo_ctx();
   c->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    c->cus = cus;
   c->stream = static_cast<hipStream_t>(hip_stream);
   if (hipHostMalloc(reinterpret_cast<void **>(&c->flags_h), sizeof(int)) != hipSuccess ||
       ensure(c, c->flags, sizeof(int)) != RFO_OK) {
@@ -471,11 +499,12 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     ctx->row_ptr_h.assign(row_ptr, row_ptr + nb + 1);
     ctx->col_h.assign(col_idx, col_idx + nnzb);
     TRY(ensure(ctx, ctx->row_ptr, (nb + 1) * sizeof(int64_t)));
-    TRY(ensure(ctx, ctx->col, nnzb * sizeof(int32_t)));
+    TRY(ensure(ctx, ctx->col, (nnzb + rfo::kStepPad) * sizeof(int32_t)));
     TRY(ensure(ctx, ctx->brow, nnzb * sizeof(int64_t)));
     TRY(ensure(ctx, ctx->tpos, nnzb * sizeof(int64_t)));
     HIPCHK(hipMemcpyAsync(ctx->row_ptr.p, row_ptr, (nb + 1) * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->col.p, col_idx, nnzb * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(hipMemsetAsync(P<int32_t>(ctx->col) + nnzb, 0, rfo::kStepPad * sizeof(int32_t), ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->brow.p, brow.data(), nnzb * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->tpos.p, tpos.data(), nnzb * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
@@ -483,9 +512,14 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
   ctx->has_h = false;
   ctx->has_grad = false;
   const size_t nval = (size_t)ctx->nnzb * ctx->bd * ctx->bd;
+  const size_t npad = (size_t)rfo::kStepPad * ctx->bd * ctx->bd;
   TRY(ensure(ctx, ctx->hraw, nval * sizeof(double)));
-  TRY(ensure(ctx, ctx->h64, nval * sizeof(double)));
-  if (precision == RFO_FP32) TRY(ensure(ctx, ctx->h32, nval * sizeof(float)));
+  TRY(ensure(ctx, ctx->h64, (nval + npad) * sizeof(double)));
+  HIPCHK(hipMemsetAsync(P<double>(ctx->h64) + nval, 0, npad * sizeof(double), ctx->stream));
+  if (precision == RFO_FP32) {
+    TRY(ensure(ctx, ctx->h32, (nval + npad) * sizeof(float)));
+    HIPCHK(hipMemsetAsync(P<float>(ctx->h32) + nval, 0, npad * sizeof(float), ctx->stream));
+  }
   HIPCHK(hipMemcpyAsync(ctx->hraw.p, values, nval * sizeof(double), hipMemcpyDefault, ctx->stream));
 
   if (e_min >= e_max) {

@@ -30,6 +30,35 @@ __device__ __forceinline__ void stv(T *p, const VecN<T, N> &v) {
   *reinterpret_cast<VecN<T, N> *>(p) = v;
 }
 
+// Streaming (non-temporal) variants for arrays read or written once per pass, so
+// that they do not displace gathered rows from the L2.
+template <typename T, int N>
+__device__ __forceinline__ VecN<T, N> ldv_nt(const T *p) {
+  VecN<T, N> r;
+  if constexpr (N == 1) {
+    r.v[0] = __builtin_nontemporal_load(p);
+  } else {
+    typedef T V __attribute__((ext_vector_type(N)));
+    const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+#pragma unroll
+    for (int q = 0; q < N; ++q) r.v[q] = v[q];
+  }
+  return r;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void stv_nt(T *p, const VecN<T, N> &x) {
+  if constexpr (N == 1) {
+    __builtin_nontemporal_store(x.v[0], p);
+  } else {
+    typedef T V __attribute__((ext_vector_type(N)));
+    V v;
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = x.v[q];
+    __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+  }
+}
+
 // Probe entry r[row][c]: sign bits (bit 1 = +1, bit 0 = -1) or dense FP64.
 __device__ __forceinline__ double probe_value(const uint64_t *sgn, const double *rden,
                                               int64_t row, int sp, int c) {
@@ -61,5 +90,13 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Load through the constant address space: with a wave-uniform address this
+// becomes a scalar (SMEM) load.  Only for data that no kernel of the same launch
+// writes.
+template <typename T>
+__device__ __forceinline__ T sld(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)(p);
+}
 
 }  // namespace rfo

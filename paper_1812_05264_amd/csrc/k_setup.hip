@@ -234,32 +234,45 @@ hipError_t launch_coefficients(double e_min, double e_max, double T, double mu, 
 }
 
 // ---- moments ---------------------------------------------------------------------
-// flags bit 2: a moment exceeded its bound or is not finite
+// flags bit 2: a moment exceeded its bound or is not finite.
+// One workgroup per (moment index, 64-probe chunk): the four waves sum strided
+// quarters of the row-group partials, then wave 0 adds the quarters in order.
 __global__ __launch_bounds__(kWG) void k_moment_reduce(const double *__restrict__ part, int ring,
                                                        int64_t k0, int count, int n_rg, int sp,
                                                        double *__restrict__ moments, int check,
                                                        double tol, int *flags) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)count * sp) return;
-  const int d = (int)(t / sp);
-  const int c = (int)(t - (int64_t)d * sp);
+  const int chunks = sp >> 6;
+  const int d = blockIdx.x / chunks;
+  const int c = (blockIdx.x - d * chunks) * 64 + (threadIdx.x & 63);
+  const int wave = threadIdx.x >> 6;
   const int64_t k = k0 + d;
   const double *src = part + (int64_t)(k % ring) * n_rg * sp + c;
-  double sum = 0.0;
-  for (int g = 0; g < n_rg; ++g) sum += src[(int64_t)g * sp];
-  moments[k * sp + c] = sum;
-  if (check) {
-    const double bound = moments[c] * (1.0 + tol) + 1e-300;
-    if (!(fabs(sum) <= bound)) atomicOr(flags, 4);
+  double s0 = 0.0, s1 = 0.0;
+  int g = wave;
+  for (; g + kWaves < n_rg; g += 2 * kWaves) {
+    s0 += src[(int64_t)g * sp];
+    s1 += src[(int64_t)(g + kWaves) * sp];
+  }
+  if (g < n_rg) s0 += src[(int64_t)g * sp];
+  __shared__ double red[kWaves][64];
+  red[wave][threadIdx.x & 63] = s0 + s1;
+  __syncthreads();
+  if (wave == 0) {
+    double sum = red[0][threadIdx.x];
+    for (int w = 1; w < kWaves; ++w) sum += red[w][threadIdx.x];
+    moments[k * sp + c] = sum;
+    if (check) {
+      const double bound = moments[c] * (1.0 + tol) + 1e-300;
+      if (!(fabs(sum) <= bound)) atomicOr(flags, 4);
+    }
   }
 }
 
 hipError_t launch_moment_reduce(const double *part, int ring, int64_t k0, int count, int n_rg,
                                 int sp, double *moments, int check, double tol, int *flags,
                                 hipStream_t s) {
-  const int64_t total = (int64_t)count * sp;
-  hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)((total + kWG - 1) / kWG)), dim3(kWG), 0, s,
-                     part, ring, k0, count, n_rg, sp, moments, check, tol, flags);
+  hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)(count * (sp >> 6))), dim3(kWG), 0, s, part,
+                     ring, k0, count, n_rg, sp, moments, check, tol, flags);
   return hipGetLastError();
 }
 

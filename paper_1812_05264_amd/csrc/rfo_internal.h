@@ -9,14 +9,17 @@ namespace rfo {
 
 constexpr int kWG = 256;            // threads per workgroup (4 wave64)
 constexpr int kWaves = kWG / 64;
+// Column-index and H_hat value arrays are allocated with kStepPad extra zero
+// blocks after nnzb so that the step kernel may read whole chunks of blocks.
+constexpr int kStepPad = 8;
 
 // ---------------------------------------------------------------------------
 // Chebyshev step: out = c1 * H_hat x + c2 * prev + beta * r, fused with
 //   moment partials   part[rg][c] += r_c . out        (when mom != 0)
 //   density accumulator acc += alpha * out              (when acc != nullptr)
 // Vectors are [n][sp] row-major (n = nb * bd scalar rows, sp = padded probes).
-// The grid is n_rg * n_pt workgroups; a workgroup owns `rows_per_wg` block rows
-// of one probe tile of 64*ppl probes.
+// The work is n_pt * n_rg units of `rows_per_wg` block rows of one probe tile of
+// 64*ppl probes, swept by a resident grid of `grid` workgroups.
 // ---------------------------------------------------------------------------
 struct StepArgs {
   const int64_t *row_ptr;
@@ -36,6 +39,9 @@ struct StepArgs {
   int sp;
   int rows_per_wg;
   int n_rg, n_pt;
+  int nt;                  // non-temporal hints on the streamed arrays
+  int rpi;                 // rows per wave iteration (1x1 blocks: 1 or 2)
+  int grid;                // workgroups (multiple of 8); part has [grid][sp]
 };
 
 // precision: 0 = fp64 (double vectors, double H), 1 = fp32 (float vectors, float H)
@@ -56,8 +62,11 @@ struct InitArgs {
   int rows_per_wg;
   int n_rg, n_pt;
   int ppl;
+  int grid;                // same grid as the step kernel
 };
 hipError_t launch_init(int precision, const InitArgs &a, hipStream_t s);
+// Resident workgroups per CU of the step kernel variant (0 on error).
+int step_blocks_per_cu(int bd, int precision, int ppl, int rpi, int nt);
 
 // ---------------------------------------------------------------------------
 // Setup kernels

@@ -36,7 +36,8 @@ def test_density_entries_match_plane_wave_sum(sc8):
     T, mu = 0.1, 0.4
     ex = exact.observables(Hd, T, mu)
     L = 8
-    site = lambda x, y, z: (x % L) + L * (y % L) + L * L * (z % L)
+    index_of = H.meta["index_of"]
+    site = lambda x, y, z: int(index_of[(x % L) + L * (y % L) + L * L * (z % L)])
     for d in [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0), (2, 1, 3), (4, 4, 4)]:
         want = cf.density_entry(L, -1.0, T, mu, d)
         for origin in [(0, 0, 0), (3, 5, 2)]:

@@ -22,6 +22,15 @@ def test_simple_cubic_structure():
     assert simple_cubic(5, disorder=1.0, config_id=4).digest() != H.digest()
 
 
+def test_simple_cubic_orderings_are_permutations():
+    a = simple_cubic(6, disorder=0.7, config_id=5, ordering="natural")
+    b = simple_cubic(6, disorder=0.7, config_id=5, ordering="morton")
+    perm = b.meta["index_of"]
+    Ad, Bd = a.to_dense(), b.to_dense()
+    assert np.array_equal(Bd[np.ix_(perm, perm)], Ad)
+    assert sorted(perm.tolist()) == list(range(216))
+
+
 def test_fcc_sphere_selection_and_shells():
     ijk = fcc_sphere(201)
     assert ijk.shape == (201, 3)
