@@ -134,6 +134,8 @@ struct Plan {
   int nt;          // non-temporal hints on streamed arrays
   int rpi;         // rows per wave iteration
   int grid;        // resident workgroups of the step kernels
+  int n_pt_step;   // probe tiles of the step kernel (BF16: tiles of 16 * ntiles probes)
+  int ntiles;      // BF16: MFMA column tiles per wave
   size_t vec_elems;
 };
 
@@ -166,12 +168,27 @@ Plan make_plan(const rfo_ctx *c) {
   // 1x1 blocks: rows per wave iteration; 9x9 blocks: blocks per gather chunk
   pl.rpi = c->bd == 1 ? 1 : 2;
   if (const char *env = getenv("RFO_RPI")) pl.rpi = atoi(env);
+  pl.n_pt_step = pl.n_pt;
+  pl.ntiles = 0;
+  int occ = 1;
+  if (c->prec == RFO_BF16) {
+    pl.ntiles = 4;
+    pl.rpi = 1;
+    if (const char *env = getenv("RFO_NTILES")) {
+      const int t = atoi(env);
+      if ((t == 4 || t == 8 || t == 16) && c->sp % (16 * t) == 0) pl.ntiles = t;
+    }
+    pl.n_pt_step = c->sp / (16 * pl.ntiles);
+    if (pl.ntiles == 16) pl.rpi = 1;
+    occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi, pl.nt));
+  } else {
+    occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi,
+                                              pl.nt));
+  }
   // one resident wave of workgroups, a multiple of 8 (one share per XCD)
-  const int occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl,
-                                                       pl.rpi, pl.nt));
   int64_t grid = (int64_t)c->cus * occ;
   if (const char *env = getenv("RFO_GRID")) grid = std::max<int64_t>(8, atoll(env));
-  const int64_t units = (int64_t)pl.n_pt * pl.n_rg;
+  const int64_t units = (int64_t)pl.n_pt_step * pl.n_rg;
   grid = std::min(grid, (units + 7) / 8 * 8);
   grid = std::max<int64_t>(8, grid / 8 * 8);
   pl.grid = (int)grid;
@@ -183,14 +200,14 @@ void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
   memset(&a, 0, sizeof(a));
   a.row_ptr = P<int64_t>(c->row_ptr);
   a.col = P<int32_t>(c->col);
-  a.hval = c->prec == RFO_FP64 ? c->h64.p : c->h32.p;
+  a.hval = c->prec == RFO_FP64 ? c->h64.p : (c->prec == RFO_FP32 ? c->h32.p : c->hbf16.p);
   a.sgn = c->signs ? P<uint64_t>(c->sgn) : nullptr;
   a.rden = c->signs ? nullptr : P<double>(c->rden);
   a.nb = c->nb;
   a.sp = c->sp;
   a.rows_per_wg = pl.rows_per_wg;
   a.n_rg = pl.n_rg;
-  a.n_pt = pl.n_pt;
+  a.n_pt = pl.n_pt_step;
   a.nt = pl.nt;
   a.rpi = pl.rpi;
   a.grid = pl.grid;
@@ -211,6 +228,11 @@ void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
 }
 
 int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 : 1; }
+
+hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::StepArgs &a) {
+  if (c->prec == RFO_BF16) return rfo::launch_step_bf16(pl.ntiles, a, c->stream);
+  return rfo::launch_step(c->bd, kernel_precision(c), pl.ppl, a, c->stream);
+}
 
 char *vec_at(rfo_ctx *c, const Plan &pl, DevBuf &b, int64_t i) {
   return static_cast<char *>(b.p) + (size_t)i * pl.vec_elems * pl.vt_bytes;
@@ -260,7 +282,7 @@ struct Checkpoints {
 int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_acc,
                 const Checkpoints *ck, size_t *n_events) {
   const int kp = kernel_precision(ctx);
-  const double tol = ctx->prec == RFO_FP64 ? 1e-6 : 1e-3;
+  const double tol = ctx->prec == RFO_FP64 ? 1e-6 : (ctx->prec == RFO_FP32 ? 1e-3 : 1e-2);
   const size_t slot = (size_t)pl.grid * ctx->sp;
   double *ring = P<double>(ctx->ring);
   double *mom = P<double>(ctx->moments);
@@ -319,7 +341,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
     sa.acc = accp;
     sa.alpha = coef + (k + 1);
     sa.part = ring + (size_t)((k + 1) % pl.ring) * slot;
-    HIPCHK(rfo::launch_step(ctx->bd, kp, pl.ppl, sa, ctx->stream));
+    HIPCHK(launch_any_step(ctx, pl, sa));
     prev = cur;
     cur = out;
     const int64_t idx = k + 1;
@@ -348,8 +370,6 @@ int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) {
   if (!(T > 0.0) || !std::isfinite(T)) return fail(ctx, RFO_E_INVALID, "T must be finite and > 0");
   if (!std::isfinite(mu)) return fail(ctx, RFO_E_INVALID, "mu must be finite");
   if (p < 1 || p > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_terms must be in [1, 2^20]");
-  if (ctx->prec == RFO_BF16)
-    return fail(ctx, RFO_E_UNSUPPORTED, "BF16 steps are not available in this build");
   HIPCHK(hipSetDevice(ctx->device));
   pl = make_plan(ctx);
   const int64_t nq = 4 * p;
@@ -520,6 +540,12 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     TRY(ensure(ctx, ctx->h32, (nval + npad) * sizeof(float)));
     HIPCHK(hipMemsetAsync(P<float>(ctx->h32) + nval, 0, npad * sizeof(float), ctx->stream));
   }
+  if (precision == RFO_BF16) {
+    const size_t pk = (size_t)27 * 8;  // bytes of one packed block
+    TRY(ensure(ctx, ctx->hbf16, ((size_t)ctx->nnzb + rfo::kStepPad) * pk));
+    HIPCHK(hipMemsetAsync(static_cast<char *>(ctx->hbf16.p) + (size_t)ctx->nnzb * pk, 0,
+                          rfo::kStepPad * pk, ctx->stream));
+  }
   HIPCHK(hipMemcpyAsync(ctx->hraw.p, values, nval * sizeof(double), hipMemcpyDefault, ctx->stream));
 
   if (e_min >= e_max) {
@@ -548,6 +574,8 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
                          P<int64_t>(ctx->tpos), ctx->nnzb, ctx->bd, e_min, e_max,
                          P<double>(ctx->h64), precision == RFO_FP32 ? P<float>(ctx->h32) : nullptr,
                          P<int>(ctx->flags), ctx->stream));
+  if (precision == RFO_BF16)
+    HIPCHK(rfo::launch_pack_bf16(P<double>(ctx->h64), ctx->hbf16.p, ctx->nnzb, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (*ctx->flags_h & 1) return fail(ctx, RFO_E_NUMERIC, "non-finite Hamiltonian values");
@@ -718,7 +746,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
         sa.beta = nullptr;
         sa.acc = nullptr;
         sa.part = nullptr;
-        HIPCHK(rfo::launch_step(ctx->bd, kp, pl.ppl, sa, ctx->stream));
+        HIPCHK(launch_any_step(ctx, pl, sa));
       }
       // reverse recurrence: zs[t] = z_{j0+1+t}; z_{p-1} = beta_{p-1} r,
       // z_{p-2} = 2 H_hat z_{p-1} + beta_{p-2} r, z_i = 2 H_hat z_{i+1} - z_{i+2} + beta_i r
@@ -739,7 +767,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
           sa.beta = beta + i;
           sa.acc = nullptr;
           sa.part = nullptr;
-          HIPCHK(rfo::launch_step(ctx->bd, kp, pl.ppl, sa, ctx->stream));
+          HIPCHK(launch_any_step(ctx, pl, sa));
         }
       }
       // G += sum_{j in segment} c_j z_{j+1} y_j^T, c_0 = 1, c_j = 2; times 2/(e_max - e_min)

@@ -1,0 +1,273 @@
+// BF16 Chebyshev step for 9x9 blocks on the matrix cores (gfx950 MFMA).
+//
+// The block product Y_I = sum_J H_hat_IJ X_J is a dense 9x9 times 9 x (probes)
+// contraction per stored block (paper: block-sparse 9x9 matrix-vector work of
+// the Chebyshev recursion), so it maps onto v_mfma_f32_16x16x16_bf16:
+//   A (16 x 16, M x K) = the block H_hat_IJ, rows and columns 9..15 zero;
+//   B (16 x 16, K x N) = rows of X_J (k = input row 0..8, rows 9..15 zero) for
+//                        16 probe columns;
+//   D (16 x 16)        = FP32 accumulator of Y_I (rows 0..8 used).
+// Lane l supplies A[l%16][4(l/16)+kk], B[4(l/16)+kk][l%16] for kk < 4 and holds
+// D[4(l/16)+i][l%16] for i < 4.  A wave covers 16*NT probes as NT MFMA tiles;
+// column n of tile t is probe p0 + n*NT + t, so a lane reads and writes NT
+// consecutive probes of a row with one vector access.  Operands are rounded to
+// BF16 (round to nearest even); accumulation, the recurrence
+// out = c1 D + c2 prev + beta r and the vectors stay FP32; moments are FP64.
+//
+// A operands are pre-packed per block: entry g*9 + m (g < 3, m < 9) holds
+// H_hat[m][4g .. 4g+3] as four BF16 (zero where the column index exceeds 8);
+// lanes with m > 8 or g = 3 supply zeros without loading.
+#include "device_util.h"
+#include "rfo_internal.h"
+
+namespace rfo {
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float f) {
+  __bf16 b = (__bf16)f;
+  return __builtin_bit_cast(short, b);
+}
+
+struct Sched2 {
+  int64_t u, hi;
+  int stride;
+  __device__ Sched2(int64_t U) {
+    const int b = blockIdx.x, G = gridDim.x;
+    const int x = b & 7;
+    stride = G >> 3;
+    const int64_t lo = U * x / 8;
+    hi = U * (x + 1) / 8;
+    u = lo + (b >> 3);
+  }
+};
+
+}  // namespace
+
+template <int NT, int U, bool NTH>
+__global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
+  constexpr int TW = 16 * NT;  // probes per wave (tile width)
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int g = lane >> 4, n = lane & 15;
+  const int sp = a.sp;
+  const int nw = sp >> 6;
+  const float *__restrict__ x = static_cast<const float *>(a.x);
+  const float *prev = static_cast<const float *>(a.prev);
+  float *out = static_cast<float *>(a.out);
+  float *acc = static_cast<float *>(a.acc);
+  const uint2 *hpack = static_cast<const uint2 *>(a.hval);
+  const bool has_prev = a.c2 != 0.0;
+  const bool add_r = a.beta != nullptr;
+  const bool mom_on = a.part != nullptr;
+  const bool need_r = add_r || mom_on;
+  const double beta = add_r ? sld(a.beta) : 0.0;
+  const float alpha = acc ? (float)sld(a.alpha) : 0.f;
+  const float c1 = (float)a.c1, c2 = (float)a.c2;
+  __shared__ double red[kWaves][4][TW];
+  double *prow = mom_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
+
+  double mom[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) mom[t] = 0.0;
+  int first_pt = -1, cur_pt = -1;
+
+  auto flush = [&](int pt) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      red[wave][g][n * NT + t] = mom[t];
+      mom[t] = 0.0;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      for (int c = lane; c < TW; c += 64) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w)
+#pragma unroll
+          for (int gg = 0; gg < 4; ++gg) s += red[w][gg][c];
+        prow[(int64_t)pt * TW + c] = s;
+      }
+    }
+    __syncthreads();
+  };
+
+  for (Sched2 sc((int64_t)a.n_pt * a.n_rg); sc.u < sc.hi; sc.u += sc.stride) {
+    const int pt = (int)(sc.u / a.n_rg);
+    const int64_t rg = sc.u - (int64_t)pt * a.n_rg;
+    if (pt != cur_pt) {
+      if (mom_on && cur_pt >= 0) flush(cur_pt);
+      if (first_pt < 0) first_pt = pt;
+      cur_pt = pt;
+    }
+    const int cp = pt * TW + n * NT;  // first probe column of this lane
+    const int64_t r0 = rg * a.rows_per_wg;
+    const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
+    for (int64_t I = r0 + wave; I < r1; I += kWaves) {
+      const int64_t beg = sld(a.row_ptr + I), end = sld(a.row_ptr + I + 1);
+      f4 d[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) d[t] = f4{0.f, 0.f, 0.f, 0.f};
+      for (int64_t nz0 = beg; nz0 < end; nz0 += U) {
+        s4 av[U];
+        VecN<float, NT> xr[U][4];
+        // every lane loads (rows and entries past the block are clamped to valid
+        // addresses and zeroed afterwards), so no load sits in a divergent branch
+        // and all of them are in flight together
+        const bool a_live = g < 3 && n < 9;
+        const int a_idx = a_live ? g * 9 + n : 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t nz = min(nz0 + u, end - 1);  // a repeated block is not accumulated
+          const int64_t J = sld(a.col + nz);
+          const uint2 p = hpack[nz * 27 + a_idx];
+          av[u] = a_live ? s4{(short)(p.x & 0xffff), (short)(p.x >> 16), (short)(p.y & 0xffff),
+                              (short)(p.y >> 16)}
+                         : s4{0, 0, 0, 0};
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk) {
+            const int rr = min(4 * g + kk, 8);
+            xr[u][kk] = ldv<float, NT>(x + (J * 9 + rr) * sp + cp);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int t = 0; t < NT; ++t)
+              xr[u][kk].v[t] = (4 * g + kk < 9) ? xr[u][kk].v[t] : 0.f;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (nz0 + u < end) {
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+              const s4 bv = s4{bf16_bits(xr[u][0].v[t]), bf16_bits(xr[u][1].v[t]),
+                               bf16_bits(xr[u][2].v[t]), bf16_bits(xr[u][3].v[t])};
+              d[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[u], bv, d[t], 0, 0, 0);
+            }
+          }
+        }
+      }
+      // epilogue: lane holds rows 4g+i (valid below 9) for probes cp .. cp+NT-1;
+      // streamed inputs of all four rows are requested first (clamped rows)
+      VecN<float, NT> pv4[4];
+      uint64_t sw4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t row = I * 9 + min(4 * g + i, 8);
+        if (has_prev) pv4[i] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
+                                   : ldv<float, NT>(prev + row * sp + cp);
+        if (need_r && a.sgn) sw4[i] = a.sgn[row * nw + (cp >> 6)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int rr = 4 * g + i;
+        if (rr >= 9) continue;
+        const int64_t row = I * 9 + rr;
+        const int64_t off = row * sp + cp;
+        const VecN<float, NT> pv = pv4[i];
+        const uint64_t sw = sw4[i];
+        VecN<double, NT> rv;
+        if (need_r && !a.sgn) rv = ldv<double, NT>(a.rden + off);
+        VecN<float, NT> o;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          double rq = 0.0;
+          if (need_r) rq = a.sgn ? (((sw >> ((cp + t) & 63)) & 1ull) ? 1.0 : -1.0) : rv.v[t];
+          float v = c1 * d[t][i];
+          if (has_prev) v = fmaf(c2, pv.v[t], v);
+          if (add_r) v = (float)((double)v + beta * rq);
+          o.v[t] = v;
+          if (mom_on) mom[t] = fma(rq, (double)v, mom[t]);
+        }
+        if (NTH) stv_nt<float, NT>(out + off, o);
+        else stv<float, NT>(out + off, o);
+        if (acc) {
+          VecN<float, NT> avv = NTH ? ldv_nt<float, NT>(acc + off) : ldv<float, NT>(acc + off);
+#pragma unroll
+          for (int t = 0; t < NT; ++t) avv.v[t] = fmaf(alpha, o.v[t], avv.v[t]);
+          if (NTH) stv_nt<float, NT>(acc + off, avv);
+          else stv<float, NT>(acc + off, avv);
+        }
+      }
+    }
+  }
+  if (mom_on) {
+    if (cur_pt >= 0) flush(cur_pt);
+    if (wave == 0) {
+      const int npt = a.n_pt;
+      for (int t = 0; t < npt; ++t) {
+        if (t >= first_pt && t <= cur_pt) continue;
+        for (int c = lane; c < TW; c += 64) prow[(int64_t)t * TW + c] = 0.0;
+      }
+    }
+  }
+}
+
+// Pack H_hat (FP64 [nnzb][9][9]) into the A-operand layout above.
+__global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hhat,
+                                                   uint2 *__restrict__ hpack, int64_t nnzb) {
+  const int64_t total = nnzb * 27;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nz = e / 27;
+    const int r = (int)(e - nz * 27);
+    const int gg = r / 9, m = r - gg * 9;
+    unsigned short v[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int col = 4 * gg + kk;
+      const float f = col < 9 ? (float)hhat[nz * 81 + m * 9 + col] : 0.f;
+      v[kk] = (unsigned short)bf16_bits(f);
+    }
+    hpack[e] = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
+                          (unsigned)v[2] | ((unsigned)v[3] << 16));
+  }
+}
+
+namespace {
+
+const void *select_bf16(int nt_tiles, int u, int nth) {
+#define RFO_BF16_CASE(T, UU)                                                        \
+  if (nt_tiles == T && u == UU)                                                     \
+    return nth ? (const void *)k_step9_bf16<T, UU, true> : (const void *)k_step9_bf16<T, UU, false>;
+  RFO_BF16_CASE(4, 1)
+  RFO_BF16_CASE(4, 2)
+  RFO_BF16_CASE(8, 1)
+  RFO_BF16_CASE(8, 2)
+  RFO_BF16_CASE(16, 1)
+#undef RFO_BF16_CASE
+  return nullptr;
+}
+
+}  // namespace
+
+int step_bf16_blocks_per_cu(int nt_tiles, int u, int nth) {
+  const void *f = select_bf16(nt_tiles, u, nth);
+  if (!f) return 0;
+  int nblk = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
+  return nblk;
+}
+
+hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s) {
+  const void *f = select_bf16(nt_tiles, a.rpi, a.nt);
+  if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
+  void *args[] = {const_cast<StepArgs *>(&a)};
+  return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);
+}
+
+hipError_t launch_pack_bf16(const double *hhat, void *hpack, int64_t nnzb, hipStream_t s) {
+  int64_t blocks = (nnzb * 27 + kWG - 1) / kWG;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(kWG), 0, s, hhat,
+                     static_cast<uint2 *>(hpack), nnzb);
+  return hipGetLastError();
+}
+
+}  // namespace rfo
