@@ -86,8 +86,9 @@ def energy_force(args):
     H, cl = build_hamiltonian(cfg)
     R = rademacher(H.n, cfg.n_probes, config_id=cfg.config_id)
     D = cl.dH_dR()
+    n_terms = args.ef_terms if args.ef_terms > 0 else cfg.n_terms
     out = {"workload": "cu16k_grad", "atoms": cl.n_atoms, "orbitals": H.n, "nnzb": H.nnzb,
-           "n_terms": cfg.n_terms, "probes": cfg.n_probes, "T_eV": cfg.T, "mu_eV": cfg.mu}
+           "n_terms": n_terms, "probes": cfg.n_probes, "T_eV": cfg.T, "mu_eV": cfg.mu}
     res = {}
     for prec in args.ef_precisions.split(","):
         eng = pkg.Engine(0)
@@ -96,7 +97,7 @@ def energy_force(args):
         import torch
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g = eng.energy_and_dEdH(cfg.T, cfg.mu, cfg.n_terms, gradient=False)
+        g = eng.energy_and_dEdH(cfg.T, cfg.mu, n_terms, gradient=False)
         f = eng.hf_forces(D)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -129,11 +130,36 @@ def main():
                     help="oracle Chebyshev steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--energy-force", type=int, default=1)
     ap.add_argument("--ef-precisions", default="fp64,fp32")
+    ap.add_argument("--ef-terms", type=int, default=0,
+                    help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
+    ap.add_argument("--only-energy-force", action="store_true",
+                    help="run only the energy_force leg (for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="time a 2 GiB device-to-device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the hot path is measured on one GPU's share; "
               "multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        n = 256 * 1024 * 1024
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                          "GB_per_s_read_plus_write": round(2 * n * 8 / dt / 1e9, 1)}))
+        return
+    if args.only_energy_force:
+        print(json.dumps({"energy_force": energy_force(args)}))
+        return
 
     import numpy as np
     import torch
@@ -168,7 +194,8 @@ def main():
     total_bytes = b_step * (p - 1) * args.steps
     value = total_bytes / wall / 1e9
     achieved = b_step / (step_ms * 1e-3) / 1e9
-    kname = f"k_step<bd1,{args.precision},ppl2>"
+    kname = ("k_step1<double, double, 2, 8, 1, true>" if args.precision == "fp64"
+             else "k_step1<float, float, 4, 8, 1, true>")
     traffic = measured_traffic(kname)
     print(f"[bench] sc64 {args.precision}: {wall / args.steps * 1e3:.1f} ms per call, step kernel "
           f"{step_ms * 1e3:.1f} us ({n_steps} steps), {achieved:.0f} GB/s, N={last['N']:.6f}",

@@ -1,0 +1,67 @@
+"""torch.autograd.Function around the library gradient, and Hellmann-Feynman forces.
+
+The Cu-like model H(R) is built with torch ops on the GPU; FermiFreeEnergy
+returns F~ from the library and hands dF~/dH to autograd, so -dF~/dR from
+autograd must equal the library's force contraction, the oracle's forces and
+central finite differences of F~ itself (h = 1e-4 A)."""
+
+import numpy as np
+import pytest
+
+from oracle import estimator as est
+from oracle import forces as ofo
+from tests.gpu_common import banner, engine_or_skip, load_hamiltonian, rel
+from workloads import cu_cluster, rademacher
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autograd_forces_match_kernel_and_oracle():
+    banner("autograd forces")
+    torch = pytest.importorskip("torch")
+    eng = engine_or_skip()
+    from paper_1812_05264_amd.autograd import free_energy
+    cl = cu_cluster(43, config_id=12)
+    H = cl.bsr()
+    R = rademacher(H.n, 6, config_id=603)
+    T, mu, p = 0.4, 0.1, 80
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    pos = torch.tensor(cl.positions, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = free_energy(cl.values_torch(pos), eng, T, mu, p)
+    F.backward()
+    f_auto = -pos.grad.cpu().numpy()
+    f_kernel = eng.hf_forces(cl.dH_dR())
+    o = est.estimate(H, R, T, mu, p, gradient=True)
+    f_oracle = ofo.hf_forces(H, o["dFdH"], cl.dH_dR())
+    assert abs(F.item() - o["F"]) < 1e-10 * abs(o["F"])
+    assert rel(f_auto, f_oracle) < 1e-10
+    assert rel(f_kernel, f_oracle) < 1e-10
+
+
+def test_forces_match_finite_differences_on_every_atom():
+    banner("position finite differences (43 atoms)")
+    eng = engine_or_skip()
+    cl = cu_cluster(43, config_id=13)
+    H = cl.bsr()
+    R = rademacher(H.n, 4, config_id=604)
+    T, mu, p, h = 0.4, 0.1, 80, 1e-4
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    eng.energy_and_dEdH(T, mu, p, gradient=False)
+    f = eng.hf_forces(cl.dH_dR())
+    assert np.max(np.abs(f.sum(axis=0))) < 1e-12 * np.max(np.abs(f))
+
+    def F_at(pos):
+        eng.set_values(cl.values_at(pos))
+        return eng.fermi_moments(T, mu, p, moments=False)["F"]
+
+    worst = 0.0
+    for a in range(cl.n_atoms):
+        for d in range(3):
+            dp = np.zeros_like(cl.positions)
+            dp[a, d] = h
+            fd = (F_at(cl.positions + dp) - F_at(cl.positions - dp)) / (2 * h)
+            worst = max(worst, abs(fd + f[a, d]))
+    print(f"max |FD + force| over all atoms: {worst:.2e} eV/A")
+    assert worst < 1e-6

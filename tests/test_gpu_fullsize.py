@@ -1,0 +1,169 @@
+"""Full-size workloads in the launch configuration the benchmark times.
+
+At these sizes the oracle cannot recompute every output beside the test, so the
+checks are (a) sampled outputs the oracle computes one by one (per-probe
+moments and traces of a few probes: on the fly for the simple-cubic lattice,
+from committed oracle fixtures for the Cu-like clusters), and (b) properties
+that hold at any size (sum of the diagonal density entries equals N, moment
+zero equals ||r||^2, forces sum to zero, forces equal central finite
+differences of F~).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import estimator as est
+from oracle import fermi as fm
+from tests.gpu_common import TOL, banner, engine_or_skip, load_hamiltonian, rel
+from workloads import rademacher
+from workloads.configs import CONFIGS, build_hamiltonian
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def fixture(name):
+    path = os.path.join(GOLDEN, f"oracle_{name}.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return json.load(open(path))
+
+
+def per_probe_traces(moments, cfg, H):
+    af, aef, bg = fm.fermi_coefficient_sets(H.e_min, H.e_max, cfg.T, cfg.mu, cfg.n_terms)
+    return moments @ af, moments @ aef, moments @ bg
+
+
+def test_sc64_bench_configuration():
+    cfg = CONFIGS["sc64"]
+    banner("sc64 full size (bench configuration)")
+    eng = engine_or_skip()
+    H, _ = build_hamiltonian(cfg)
+    R = rademacher(H.n, cfg.n_probes, config_id=cfg.config_id)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    g = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True, density=True)
+    assert np.all(g["moments"][:, 0] == H.n)
+    # sampled outputs: first and last probe, every moment, against the oracle
+    cols = [0, cfg.n_probes - 1]
+    o = est.moments(est.mapped_hamiltonian(H), R[:, cols], cfg.n_terms)
+    for i, c in enumerate(cols):
+        assert rel(g["moments"][c], o[i]) < TOL
+    # properties at full size: N from the moments equals the traced density
+    rows = H.block_rows()
+    diag = g["density"][rows == H.col_idx, 0, 0]
+    assert abs(diag.sum() - g["N"]) < 1e-10 * abs(g["N"])
+    Nc, Ec, Fc = per_probe_traces(g["moments"], cfg, H)
+    w = np.full(cfg.n_probes, 1.0 / cfg.n_probes)
+    for val, key in ((Nc, "N"), (Ec, "E"), (Fc, "F")):
+        assert abs(w @ val - g[key]) < 1e-11 * abs(g[key])
+
+
+def _cu_forward(name, precision):
+    fx = fixture(name)
+    cfg = CONFIGS[fx["config"]]
+    eng = engine_or_skip()
+    H, cl = build_hamiltonian(cfg)
+    assert H.digest() == fx["input_digest"], "input differs from the fixture's"
+    R = rademacher(H.n, fx["n_probes_drawn"], config_id=cfg.config_id)
+    load_hamiltonian(eng, H, precision=precision)
+    eng.set_probes(R)
+    return fx, cfg, eng, H, cl, R
+
+
+@pytest.mark.parametrize("precision", ["fp64"])
+def test_cu4k_configuration(precision):
+    banner("cu4k full size")
+    fx, cfg, eng, H, cl, R = _cu_forward("cu4k", precision)
+    g = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True, density=True)
+    cols = fx["columns"]
+    Nc, Ec, Fc = per_probe_traces(g["moments"][cols], cfg, H)
+    for got, key in ((Nc, "N_c"), (Ec, "E_c"), (Fc, "F_c")):
+        assert rel(got, fx[key]) < TOL, key
+    assert rel(g["moments"][cols][:, fx["sample_k"]], fx["moments_sampled"]) < TOL
+    rows = H.block_rows()
+    diag = np.einsum("zii->z", g["density"][rows == H.col_idx])
+    assert abs(diag.sum() - g["N"]) < 1e-10 * abs(g["N"])
+
+
+def test_cu16k_configuration_fp64_and_bf16():
+    banner("cu16k full size: FP64 parity and BF16 error")
+    fx, cfg, eng, H, cl, R = _cu_forward("cu16k", "fp64")
+    cols = fx["columns"]
+    g64 = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True)
+    Nc, Ec, Fc = per_probe_traces(g64["moments"][cols], cfg, H)
+    n_at = cl.n_atoms
+    for got, key in ((Nc, "N_c"), (Ec, "E_c"), (Fc, "F_c")):
+        assert rel(got, fx[key]) < TOL, key
+        assert np.max(np.abs(np.asarray(got) - fx[key])) / n_at < 1e-6   # eV/atom, per probe
+    load_hamiltonian(eng, H, precision="bf16")
+    eng.set_probes(R)
+    g16 = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True)
+    Nb, Eb, Fb = per_probe_traces(g16["moments"][cols], cfg, H)
+    dF = np.max(np.abs(np.asarray(Fb) - fx["F_c"])) / n_at
+    dE = np.max(np.abs(np.asarray(Eb) - fx["E_c"])) / n_at
+    print(f"cu16k BF16 vs FP64 oracle, per probe: |dF| {dF:.2e} eV/atom, |dE| {dE:.2e} eV/atom; "
+          f"all-probe F {abs(g16['F'] - g64['F']) / n_at:.2e} eV/atom")
+    assert dF < 1e-2 and dE < 1e-2
+
+
+@pytest.fixture(scope="module")
+def cu16k_grad():
+    banner("cu16k gradient setup")
+    fx, cfg, eng, H, cl, R = _cu_forward("cu16k_grad16", "fp64")
+    T, mu, p = cfg.T, cfg.mu, cfg.n_terms
+    g = eng.fermi_moments(T, mu, p, moments=True)
+    e = eng.energy_and_dEdH(T, mu, p, gradient=False)
+    f = eng.hf_forces(cl.dH_dR())
+    return {"fx": fx, "cfg": cfg, "eng": eng, "H": H, "cl": cl, "g": g, "e": e, "f": f}
+
+
+def test_cu16k_gradient_energy_and_invariants(cu16k_grad):
+    banner("cu16k gradient: FP64 energy vs oracle, invariants")
+    d = cu16k_grad
+    fx, cfg, H, cl, g, e, f = d["fx"], d["cfg"], d["H"], d["cl"], d["g"], d["e"], d["f"]
+    _, _, Fc = per_probe_traces(g["moments"][fx["columns"]], cfg, H)
+    assert rel(Fc, fx["F_c"]) < TOL
+    assert np.max(np.abs(np.asarray(Fc) - fx["F_c"])) / cl.n_atoms < 1e-6
+    assert abs(e["F"] - g["F"]) < 1e-12 * abs(g["F"])
+    assert np.max(np.abs(f.sum(axis=0))) < 1e-9 * np.max(np.abs(f))
+
+
+def _fd_atoms(d, atoms):
+    eng, cl, cfg, f = d["eng"], d["cl"], d["cfg"], d["f"]
+    T, mu, p, h = cfg.T, cfg.mu, cfg.n_terms, 1e-4
+
+    def F_at(pos):
+        eng.set_values(cl.values_at(pos))
+        return eng.fermi_moments(T, mu, p, moments=False)["F"]
+
+    worst = 0.0
+    rng = np.random.default_rng(7)
+    for a in atoms:
+        k = int(rng.integers(3))
+        dp = np.zeros_like(cl.positions)
+        dp[a, k] = h
+        fd = (F_at(cl.positions + dp) - F_at(cl.positions - dp)) / (2 * h)
+        worst = max(worst, abs(fd + f[a, k]))
+    eng.set_values(cl.values_at(cl.positions))
+    # rounding of F (~1e-13 relative) over 2h sets the finite-difference floor
+    floor = 1e-13 * abs(d["g"]["F"]) / (2 * h)
+    return worst, floor
+
+
+@pytest.mark.parametrize("group", ["low_coordination", "bulk"])
+def test_cu16k_forces_match_finite_differences(cu16k_grad, group):
+    banner(f"cu16k forces vs central differences: 16 {group} atoms")
+    d = cu16k_grad
+    coord = np.diff(d["H"].row_ptr)
+    n_at = d["cl"].n_atoms
+    if group == "low_coordination":
+        atoms = np.lexsort((np.arange(n_at), coord))[:16]
+    else:
+        atoms = np.nonzero(coord == coord.max())[0][:16]
+    worst, floor = _fd_atoms(d, atoms)
+    print(f"cu16k {group}: worst |FD + force| {worst:.2e} eV/A (rounding floor ~{floor:.1e})")
+    assert worst < max(1e-4, 20 * floor)

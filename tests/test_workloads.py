@@ -79,3 +79,12 @@ def test_rademacher_deterministic_pm1():
     assert set(np.unique(R)) == {-1.0, 1.0}
     assert np.array_equal(R, rademacher(100, 16, config_id=2))
     assert not np.array_equal(R, rademacher(100, 16, config_id=3))
+
+
+def test_cu_mu_matches_its_derivation():
+    import json
+    import os
+    from workloads.configs import CU_MU
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cu_mu.json")))
+    assert CU_MU == d["mu_eV"]
+    assert abs(d["electrons_per_atom_at_mu"] - 11.0) < 0.01
