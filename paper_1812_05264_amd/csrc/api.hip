@@ -36,7 +36,8 @@ struct rfo_ctx {
   double e_min = 0.0, e_max = 0.0;
   std::vector<int64_t> row_ptr_h;
   std::vector<int32_t> col_h;
-  DevBuf row_ptr, col, brow, tpos, hraw, h64, h32, hbf16, gscratch;
+  DevBuf row_ptr, col, brow, tpos, hraw, h64, h32, hbf16, gscratch, nz_up, nz_low;
+  int64_t n_up = 0, n_low = 0;
 
   // probes
   bool has_r = false;
@@ -58,7 +59,7 @@ struct rfo_ctx {
 
   ~rfo_ctx() {
     hipSetDevice(device);
-    DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch,
+    DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch, &nz_up, &nz_low,
                      &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
                      &costab, &small, &flags, &G, &dHdR, &forces};
     for (DevBuf *b : all)
@@ -228,6 +229,12 @@ void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
 }
 
 int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 : 1; }
+
+int sddmm_ppl(const rfo_ctx *c) {
+  int ppl = (c->sp % 128 == 0) ? 2 : 1;
+  if (const char *env = getenv("RFO_SDDMM_PPL")) ppl = atoi(env) == 2 && c->sp % 128 == 0 ? 2 : 1;
+  return ppl;
+}
 
 hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::StepArgs &a) {
   if (c->prec == RFO_BF16) return rfo::launch_step_bf16(pl.ntiles, a, c->stream);
@@ -527,6 +534,18 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     HIPCHK(hipMemsetAsync(P<int32_t>(ctx->col) + nnzb, 0, rfo::kStepPad * sizeof(int32_t), ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->brow.p, brow.data(), nnzb * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(hipMemcpyAsync(ctx->tpos.p, tpos.data(), nnzb * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    // blocks on and above the block diagonal (computed by the gradient) and below it (mirrored)
+    std::vector<int64_t> up, low;
+    up.reserve(nnzb / 2 + nb);
+    low.reserve(nnzb / 2);
+    for (int64_t z = 0; z < nnzb; ++z) (brow[z] <= (int64_t)col_idx[z] ? up : low).push_back(z);
+    TRY(ensure(ctx, ctx->nz_up, up.size() * sizeof(int64_t)));
+    TRY(ensure(ctx, ctx->nz_low, std::max<size_t>(1, low.size()) * sizeof(int64_t)));
+    HIPCHK(hipMemcpyAsync(ctx->nz_up.p, up.data(), up.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    if (!low.empty())
+      HIPCHK(hipMemcpyAsync(ctx->nz_low.p, low.data(), low.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
+    ctx->n_up = (int64_t)up.size();
+    ctx->n_low = (int64_t)low.size();
     HIPCHK(hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
   }
   ctx->has_h = false;
@@ -663,6 +682,8 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
     a.rest = 1.0;
     a.G = P<double>(ctx->G);
     a.accumulate = 0;
+    a.nzlist = nullptr;
+    a.ppl = sddmm_ppl(ctx);
     HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
     ctx->has_grad = false;  // G now holds the density
     TRY(copy_out(ctx, density_out, ctx->G.p, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
@@ -790,6 +811,10 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       a.rest = 2.0;
       a.G = P<double>(ctx->G);
       a.accumulate = (q == Q - 1) ? 0 : 1;
+      // the full gradient is symmetric: blocks on and above the diagonal only
+      a.nzlist = P<int64_t>(ctx->nz_up);
+      a.nlist = ctx->n_up;
+      a.ppl = sddmm_ppl(ctx);
       HIPCHK(rfo::launch_sddmm(kp, a, ctx->stream));
       if (q > 0) {
         // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}
@@ -798,6 +823,9 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       }
     }
   }
+  if (P1 > 0)
+    HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
+                              P<double>(ctx->G), ctx->stream));
   TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
   TRY(check_flags_and_finish(ctx, n_events));

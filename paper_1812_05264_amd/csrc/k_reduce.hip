@@ -16,14 +16,16 @@
 
 namespace rfo {
 
-template <int BD, typename VT>
+template <int BD, typename VT, int PPL>
 __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t nz = (int64_t)blockIdx.x * kWaves + wave;
-  if (nz >= a.nnzb) return;
-  const int64_t I = a.brow[nz];
-  const int64_t J = a.col[nz];
+  const int64_t widx = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t total = a.nzlist ? a.nlist : a.nnzb;
+  if (widx >= total) return;
+  const int64_t nz = a.nzlist ? sld(a.nzlist + widx) : widx;
+  const int64_t I = sld(a.brow + nz);
+  const int64_t J = sld(a.col + nz);
   const int sp = a.sp;
   double s[BD][BD];
 #pragma unroll
@@ -35,18 +37,31 @@ __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
     const double coef = a.scale * ((a.j0 + t == 0) ? a.first : a.rest);
     const VT *X = static_cast<const VT *>(a.xbase) + (int64_t)t * a.xstride;
     const VT *Y = a.ybase ? static_cast<const VT *>(a.ybase) + (int64_t)t * a.ystride : nullptr;
-    for (int c = lane; c < sp; c += 64) {
-      const double wc = a.w[c] * coef;
-      double xa[BD], yb[BD];
+    for (int c = lane * PPL; c < sp; c += 64 * PPL) {
+      VecN<VT, PPL> xv[BD], yv[BD];
 #pragma unroll
-      for (int i = 0; i < BD; ++i) xa[i] = wc * (double)X[(I * BD + i) * sp + c];
+      for (int i = 0; i < BD; ++i) xv[i] = ldv<VT, PPL>(X + (I * BD + i) * sp + c);
+      if (Y) {
 #pragma unroll
-      for (int j = 0; j < BD; ++j)
-        yb[j] = Y ? (double)Y[(J * BD + j) * sp + c] : probe_value(a.sgn, a.rden, J * BD + j, sp, c);
+        for (int j = 0; j < BD; ++j) yv[j] = ldv<VT, PPL>(Y + (J * BD + j) * sp + c);
+      } else {
 #pragma unroll
-      for (int i = 0; i < BD; ++i)
+        for (int j = 0; j < BD; ++j)
 #pragma unroll
-        for (int j = 0; j < BD; ++j) s[i][j] = fma(xa[i], yb[j], s[i][j]);
+          for (int q = 0; q < PPL; ++q)
+            yv[j].v[q] = (VT)probe_value(a.sgn, a.rden, J * BD + j, sp, c + q);
+      }
+#pragma unroll
+      for (int q = 0; q < PPL; ++q) {
+        const double wc = a.w[c + q] * coef;
+        double xa[BD];
+#pragma unroll
+        for (int i = 0; i < BD; ++i) xa[i] = wc * (double)xv[i].v[q];
+#pragma unroll
+        for (int i = 0; i < BD; ++i)
+#pragma unroll
+          for (int j = 0; j < BD; ++j) s[i][j] = fma(xa[i], (double)yv[j].v[q], s[i][j]);
+      }
     }
   }
   double *g = a.G + nz * (BD * BD);
@@ -60,18 +75,50 @@ __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
   }
 }
 
+template <int BD, typename VT>
+static void launch_sddmm_t(const SddmmArgs &a, dim3 grid, hipStream_t s) {
+  if (a.ppl == 2) hipLaunchKernelGGL((k_sddmm<BD, VT, 2>), grid, dim3(kWG), 0, s, a);
+  else hipLaunchKernelGGL((k_sddmm<BD, VT, 1>), grid, dim3(kWG), 0, s, a);
+}
+
 hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s) {
-  const dim3 grid((unsigned)((a.nnzb + kWaves - 1) / kWaves)), block(kWG);
-  if (a.nnzb == 0) return hipSuccess;
+  const int64_t total = a.nzlist ? a.nlist : a.nnzb;
+  if (total == 0) return hipSuccess;
+  if (a.ppl == 2 && (a.sp % 128) != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((total + kWaves - 1) / kWaves));
   if (a.bd == 1) {
-    if (precision == 0) hipLaunchKernelGGL((k_sddmm<1, double>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_sddmm<1, float>), grid, block, 0, s, a);
+    if (precision == 0) launch_sddmm_t<1, double>(a, grid, s);
+    else launch_sddmm_t<1, float>(a, grid, s);
   } else if (a.bd == 9) {
-    if (precision == 0) hipLaunchKernelGGL((k_sddmm<9, double>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_sddmm<9, float>), grid, block, 0, s, a);
+    if (precision == 0) launch_sddmm_t<9, double>(a, grid, s);
+    else launch_sddmm_t<9, float>(a, grid, s);
   } else {
     return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kWG) void k_mirror(const int64_t *__restrict__ nzlist, int64_t nlist,
+                                                const int64_t *__restrict__ tpos, int bd,
+                                                double *__restrict__ G) {
+  const int bb = bd * bd;
+  const int64_t total = nlist * bb;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = e / bb;
+    const int r = (int)(e - k * bb);
+    const int i = r / bd, j = r - (r / bd) * bd;
+    const int64_t nz = nzlist[k];
+    G[nz * bb + i * bd + j] = G[tpos[nz] * bb + j * bd + i];
+  }
+}
+
+hipError_t launch_mirror(const int64_t *nzlist, int64_t nlist, const int64_t *tpos, int bd,
+                         double *G, hipStream_t s) {
+  if (nlist == 0) return hipSuccess;
+  int64_t blocks = (nlist * bd * bd + kWG - 1) / kWG;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_mirror, dim3((unsigned)blocks), dim3(kWG), 0, s, nzlist, nlist, tpos, bd, G);
   return hipGetLastError();
 }
 

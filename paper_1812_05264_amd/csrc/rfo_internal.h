@@ -125,8 +125,14 @@ struct SddmmArgs {
   double scale, first, rest;
   double *G;
   int accumulate;
+  const int64_t *nzlist;   // blocks to compute (nullptr = all nnzb)
+  int64_t nlist;
+  int ppl;                 // probes per lane per load (1 or 2)
 };
 hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s);
+// G[nz] = G[tpos[nz]]^T for the listed blocks (completes a symmetric gradient).
+hipError_t launch_mirror(const int64_t *nzlist, int64_t nlist, const int64_t *tpos, int bd,
+                         double *G, hipStream_t s);
 // Hellmann-Feynman forces from G and d H_IJ / d R_I blocks.
 hipError_t launch_forces(const int64_t *row_ptr, const int64_t *tpos,
                          const double *G, const double *D, int64_t nb, int bd,
