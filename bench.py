@@ -10,7 +10,8 @@ the density accumulator, moment reductions, traces and the density blocks.
 metric: Chebyshev H.V step GB/s = algorithmic bytes of all H.V steps of the timed
 calls / wall time of those calls.  Algorithmic bytes per step: H_hat values,
 column indices and row pointers once, y_k once, y_{k-1} once, y_{k+1} once,
-the accumulator read and written once, the packed probe bits once.
+the packed probe bits once, and the accumulator read and written once per
+update (one update per three steps, plus one at the last step).
 
 Also reported on the same line:
   roofline      for the Chebyshev step kernel, from HIP events around its launches
@@ -33,11 +34,22 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def step_bytes(H, s, vt_bytes, mt_bytes, density):
+def acc_updates(p):
+    """Steps (of the p - 1) that read and write the density accumulator: the
+    library adds the terms of three consecutive steps in one pass, and whatever
+    is left at the last step."""
+    done, n = 0, 0
+    for j in range(1, p):
+        if j - done == 3 or j == p - 1:
+            done, n = j, n + 1
+    return n
+
+
+def step_bytes(H, s, vt_bytes, mt_bytes, density, p=None):
     bd = H.block_dim
     h = H.nnzb * bd * bd * mt_bytes + H.nnzb * 4 + (H.n_block_rows + 1) * 8
     vec = H.n * s * vt_bytes
-    streams = 3 + (2 if density else 0)
+    streams = 3.0 + (2.0 * acc_updates(p) / (p - 1) if density else 0.0)
     return h + streams * vec + H.n * s / 8.0
 
 
@@ -175,7 +187,7 @@ def main():
     eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 1, H.e_min, H.e_max, args.precision)
     eng.set_probes(R)
     vt = 8 if args.precision == "fp64" else 4
-    b_step = step_bytes(H, s, vt, vt, density=True)
+    b_step = step_bytes(H, s, vt, vt, density=True, p=p)
     dens = torch.empty((H.nnzb, 1, 1), dtype=torch.float64, device="cuda")
 
     for _ in range(args.warmup):

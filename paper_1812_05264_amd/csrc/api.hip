@@ -237,6 +237,9 @@ int sddmm_ppl(const rfo_ctx *c) {
 }
 
 hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::StepArgs &a) {
+  // three accumulator terms need y_{k-1}, which the first pass does not have
+  if (a.acc_terms < 0 || a.acc_terms > 3 || (a.acc_terms == 3 && a.c2 == 0.0))
+    return hipErrorInvalidValue;
   if (c->prec == RFO_BF16) return rfo::launch_step_bf16(pl.ntiles, a, c->stream);
   return rfo::launch_step(c->bd, kernel_precision(c), pl.ppl, a, c->stream);
 }
@@ -331,6 +334,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
   fill_step(ctx, pl, sa);
   char *cur = A, *prev = B;
   int64_t batch_start = 1;
+  int64_t acc_done = 0;  // the accumulator holds alpha_j y_j for j <= acc_done
   size_t ev = 0;
   for (int64_t k = 0; k + 1 < p; ++k) {
     if (ctx->timing && k + 1 == batch_start) {
@@ -345,8 +349,13 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
     sa.c1 = (k == 0) ? 1.0 : 2.0;
     sa.c2 = (k == 0) ? 0.0 : -1.0;
     sa.beta = nullptr;
+    // terms y_{acc_done+1} .. y_{k+1} wait; add them when three are held by the
+    // pass (y_{k-1}, y_k, y_{k+1}) or at the last step
+    const int64_t pending = k + 1 - acc_done;
     sa.acc = accp;
-    sa.alpha = coef + (k + 1);
+    sa.acc_terms = (accp && (pending == 3 || k + 2 == p)) ? (int)pending : 0;
+    sa.alpha = coef + (acc_done + 1);
+    if (sa.acc_terms) acc_done = k + 1;
     sa.part = ring + (size_t)((k + 1) % pl.ring) * slot;
     HIPCHK(launch_any_step(ctx, pl, sa));
     prev = cur;

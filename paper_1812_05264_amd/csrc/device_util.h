@@ -89,6 +89,31 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Density accumulator update with the m (1..3) newest terms of the recurrence
+// that one pass holds, oldest first: y_{k-1} (p), y_k (x), y_{k+1} (o); al[i]
+// is the coefficient of the i-th of those m terms.  Adding them in this order
+// gives the same rounding as adding one term per pass.
+template <typename VT, int N>
+__device__ __forceinline__ VecN<VT, N> add_terms(VecN<VT, N> av, int m, const VT (&al)[3],
+                                                 const VecN<VT, N> &p, const VecN<VT, N> &x,
+                                                 const VecN<VT, N> &o) {
+  int i = 0;
+  if (m >= 3) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) av.v[q] = fma(al[0], p.v[q], av.v[q]);
+    i = 1;
+  }
+  if (m >= 2) {
+    const VT c = al[i++];
+#pragma unroll
+    for (int q = 0; q < N; ++q) av.v[q] = fma(c, x.v[q], av.v[q]);
+  }
+  const VT c = al[i];
+#pragma unroll
+  for (int q = 0; q < N; ++q) av.v[q] = fma(c, o.v[q], av.v[q]);
+  return av;
+}
+
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // Load through the constant address space: with a wave-uniform address this

@@ -65,7 +65,10 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   const bool mom_on = a.part != nullptr;
   const bool need_r = add_r || mom_on;
   const double beta = add_r ? sld(a.beta) : 0.0;
-  const float alpha = acc ? (float)sld(a.alpha) : 0.f;
+  const int m = acc ? a.acc_terms : 0;
+  float al[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) al[i] = i < m ? (float)sld(a.alpha + i) : 0.f;
   const float c1 = (float)a.c1, c2 = (float)a.c2;
   __shared__ double red[kWaves][4][TW];
   double *prow = mom_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
@@ -154,13 +157,14 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
       }
       // epilogue: lane holds rows 4g+i (valid below 9) for probes cp .. cp+NT-1;
       // streamed inputs of all four rows are requested first (clamped rows)
-      VecN<float, NT> pv4[4];
+      VecN<float, NT> pv4[4], xs4[4];
       uint64_t sw4[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int64_t row = I * 9 + min(4 * g + i, 8);
         if (has_prev) pv4[i] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
                                    : ldv<float, NT>(prev + row * sp + cp);
+        if (m >= 2) xs4[i] = ldv<float, NT>(x + row * sp + cp);
         if (need_r && a.sgn) sw4[i] = a.sgn[row * nw + (cp >> 6)];
       }
 #pragma unroll
@@ -186,10 +190,9 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
         }
         if (NTH) stv_nt<float, NT>(out + off, o);
         else stv<float, NT>(out + off, o);
-        if (acc) {
+        if (m > 0) {
           VecN<float, NT> avv = NTH ? ldv_nt<float, NT>(acc + off) : ldv<float, NT>(acc + off);
-#pragma unroll
-          for (int t = 0; t < NT; ++t) avv.v[t] = fmaf(alpha, o.v[t], avv.v[t]);
+          avv = add_terms<float, NT>(avv, m, al, pv, xs4[i], o);
           if (NTH) stv_nt<float, NT>(acc + off, avv);
           else stv<float, NT>(acc + off, avv);
         }

@@ -1,8 +1,10 @@
 // Chebyshev step kernels: one fused pass per term of the three-term recurrence
 //   y_{k+1} = 2 H_hat y_k - y_{k-1}   (y_1 = H_hat y_0)
 // with the moment partials r_c . y_{k+1} and the density accumulator
-// acc += alpha_{k+1} y_{k+1} folded into the same pass (paper: Polynomial
-// approximation, Chebyshev recursion with S = I; Random approximation).
+// acc = sum_k alpha_k y_k folded into the same pass (paper: Polynomial
+// approximation, Chebyshev recursion with S = I; Random approximation).  A pass
+// holds y_{k-1}, y_k and y_{k+1}, so the accumulator is updated on every third
+// pass only, with three terms at once.
 // The reverse recurrence of the free-energy gradient uses the same kernel with
 // an added beta_j r term.
 //
@@ -102,7 +104,10 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const bool mom_on = a.part != nullptr;
   const bool need_r = add_r || mom_on;
   const double beta = add_r ? sld(a.beta) : 0.0;
-  const VT alpha = acc ? (VT)sld(a.alpha) : (VT)0;
+  const int m = acc ? a.acc_terms : 0;
+  VT al[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
   const VT c1 = (VT)a.c1, c2 = (VT)a.c2;
   __shared__ double red[kWaves][64 * PPL];
   double *prow = mom_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
@@ -131,13 +136,14 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
         beg[r] = sld(a.row_ptr + Ir[r]);
         end[r] = sld(a.row_ptr + Ir[r] + 1);
       }
-      VecN<VT, PPL> pv[RPI];
+      VecN<VT, PPL> pv[RPI], xs[RPI];
       uint64_t sw[RPI];
       VecN<double, PPL> rv[RPI];
 #pragma unroll
       for (int r = 0; r < RPI; ++r) {
         const int64_t off = Ir[r] * sp + c0;
         if (has_prev) pv[r] = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        if (m >= 2) xs[r] = ldv<VT, PPL>(x + off);
         if (need_r) {
           if (a.sgn) sw[r] = a.sgn[Ir[r] * nw + (c0 >> 6)];
           else rv[r] = ldv<double, PPL>(a.rden + off);
@@ -204,10 +210,9 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
         }
         if (NT) stv_nt<VT, PPL>(out + off, o);
         else stv<VT, PPL>(out + off, o);
-        if (acc) {
+        if (m > 0) {
           VecN<VT, PPL> av = NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
-#pragma unroll
-          for (int q = 0; q < PPL; ++q) av.v[q] = fma(alpha, o.v[q], av.v[q]);
+          av = add_terms<VT, PPL>(av, m, al, pv[r], xs[r], o);
           if (NT) stv_nt<VT, PPL>(acc + off, av);
           else stv<VT, PPL>(acc + off, av);
         }
@@ -246,7 +251,10 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   const bool mom_on = a.part != nullptr;
   const bool need_r = add_r || mom_on;
   const double beta = add_r ? sld(a.beta) : 0.0;
-  const VT alpha = acc ? (VT)sld(a.alpha) : (VT)0;
+  const int m = acc ? a.acc_terms : 0;
+  VT al[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
   const VT c1 = (VT)a.c1, c2 = (VT)a.c2;
   __shared__ double red[kWaves][64 * PPL];
   __shared__ MT hs[kWaves][CH];
@@ -320,8 +328,9 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
       for (int i = 0; i < BD; ++i) {
         const int64_t row = I * BD + i;
         const int64_t off = row * sp + c0;
-        VecN<VT, PPL> pv;
+        VecN<VT, PPL> pv, xs;
         if (has_prev) pv = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        if (m >= 2) xs = ldv<VT, PPL>(x + off);
         double r[PPL];
         if (need_r) {
           if (a.sgn) {
@@ -345,10 +354,9 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
         }
         if (NT) stv_nt<VT, PPL>(out + off, o);
         else stv<VT, PPL>(out + off, o);
-        if (acc) {
+        if (m > 0) {
           VecN<VT, PPL> av = NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
-#pragma unroll
-          for (int q = 0; q < PPL; ++q) av.v[q] = fma(alpha, o.v[q], av.v[q]);
+          av = add_terms<VT, PPL>(av, m, al, pv, xs, o);
           if (NT) stv_nt<VT, PPL>(acc + off, av);
           else stv<VT, PPL>(acc + off, av);
         }

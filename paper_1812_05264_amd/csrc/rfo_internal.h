@@ -16,7 +16,10 @@ constexpr int kStepPad = 8;
 // ---------------------------------------------------------------------------
 // Chebyshev step: out = c1 * H_hat x + c2 * prev + beta * r, fused with
 //   moment partials   part[rg][c] += r_c . out        (when mom != 0)
-//   density accumulator acc += alpha * out              (when acc != nullptr)
+//   density accumulator acc += sum_i alpha[i] y_{k+2-m+i}, i < m (when acc != nullptr
+//     and m = acc_terms > 0): the pass holds y_{k-1} (prev), y_k (the row of x)
+//     and y_{k+1} (out), so the accumulator is read and written once per up to
+//     three terms; the terms are added oldest first, as one at a time would be.
 // Vectors are [n][sp] row-major (n = nb * bd scalar rows, sp = padded probes).
 // The work is n_pt * n_rg units of `rows_per_wg` block rows of one probe tile of
 // 64*ppl probes, swept by a resident grid of `grid` workgroups.
@@ -33,7 +36,8 @@ struct StepArgs {
   double c1, c2;
   const double *beta;      // device scalar: adds beta * r when non-null
   void *acc;               // density accumulator or nullptr
-  const double *alpha;     // device scalar used with acc
+  const double *alpha;     // device array: alpha^f of the acc_terms newest terms, oldest first
+  int acc_terms;           // 0..3; 3 needs prev (c2 != 0)
   double *part;            // [n_rg][sp] moment partials (ring slot) or nullptr
   int64_t nb;              // block rows
   int sp;

@@ -43,6 +43,23 @@ def test_fermi_moments_match_oracle(name):
     assert rel(g["density"], o["density"]) < TOL
 
 
+@pytest.mark.parametrize("bd", [1, 9])
+def test_density_short_series(bd):
+    """The accumulator takes up to three terms per pass; series of 1..8 terms hit
+    every way the last pass can end."""
+    banner(f"density short series bd={bd}")
+    eng = engine_or_skip()
+    H = simple_cubic(6, disorder=0.5, config_id=24) if bd == 1 else cu_cluster(19, config_id=24).bsr()
+    R = rademacher(H.n, 72, config_id=501)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    for p in range(1, 9):
+        g = eng.fermi_moments(0.2, 0.1, p, moments=True, density=True)
+        o = est.estimate(H, R, 0.2, 0.1, p, density=True)
+        assert rel(g["moments"], o["moments"]) < TOL, p
+        assert rel(g["density"], o["density"]) < TOL, p
+
+
 def test_config_sc8_against_closed_form():
     # the simple-cubic config: estimate within ~5 sigma of the exact band, trace identities exact
     banner("sc8 closed form")

@@ -58,6 +58,19 @@ def test_bf16_mfma_against_oracle(name, atoms, s, p):
     assert em < 3e-2 and ed < 3e-2 and eN < 1e-2 and eE < 1e-2
 
 
+def test_bf16_density_short_series():
+    banner("bf16 density short series")
+    eng = engine_or_skip()
+    H = cu_cluster(55, config_id=23).bsr()
+    R = rademacher(H.n, 64, config_id=603)
+    load_hamiltonian(eng, H, precision="bf16")
+    eng.set_probes(R)
+    for p in range(1, 8):
+        g = eng.fermi_moments(0.3, 0.2, p, density=True)
+        o = est.estimate(H, R, 0.3, 0.2, p, density=True)
+        assert rel(g["density"], o["density"]) < 3e-2, p
+
+
 def test_bf16_gradient_against_fp64():
     banner("bf16 gradient")
     eng = engine_or_skip()
