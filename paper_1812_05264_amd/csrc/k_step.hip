@@ -160,7 +160,11 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
 #pragma unroll
         for (int r = 0; r < RPI; ++r)
 #pragma unroll
-          for (int u = 0; u < U; ++u) J[r][u] = sld(a.col + beg[r] + u);
+          for (int u = 0; u < U; ++u) {
+            // slots past the row's end re-read the row's own vector (a cache hit)
+            const int64_t Jc = sld(a.col + beg[r] + u);
+            J[r][u] = beg[r] + u < end[r] ? Jc : Ir[r];
+          }
 #pragma unroll
         for (int r = 0; r < RPI; ++r)
 #pragma unroll
@@ -181,7 +185,10 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
           int64_t J[U];
           VecN<VT, PPL> xv[U];
 #pragma unroll
-          for (int u = 0; u < U; ++u) J[u] = sld(a.col + nz0 + u);
+          for (int u = 0; u < U; ++u) {
+            const int64_t Jc = sld(a.col + nz0 + u);
+            J[u] = nz0 + u < end[r] ? Jc : Ir[r];
+          }
 #pragma unroll
           for (int u = 0; u < U; ++u) xv[u] = ldv<VT, PPL>(x + J[u] * sp + c0);
 #pragma unroll

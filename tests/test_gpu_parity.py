@@ -13,7 +13,7 @@ from oracle import estimator as est
 from oracle import forces as ofo
 from oracle import trunc
 from tests.gpu_common import TOL, banner, engine_or_skip, load_hamiltonian, rel
-from workloads import cu_cluster, identity_probes, rademacher, simple_cubic
+from workloads import cu_cluster, identity_probes, rademacher, random_graph, simple_cubic
 
 pytestmark = pytest.mark.gpu
 
@@ -23,6 +23,8 @@ CASES = {
     "sc12_ragged": (lambda: simple_cubic(12, disorder=0.8, config_id=21), 200, 0.1, 0.2, 300),
     "cu55_ragged": (lambda: cu_cluster(55, config_id=22).bsr(), 100, 0.3, 0.5, 200),
     "cu201": (lambda: cu_cluster(201, config_id=23).bsr(), 128, 0.2, 0.1, 160),
+    # uneven rows (1 to 26 entries, one isolated site): the general row layout
+    "graph700_uneven": (lambda: random_graph(700, config_id=31), 136, 0.5, 0.3, 150),
 }
 
 
@@ -100,6 +102,7 @@ GRAD_CASES = {
     "cu55_grad": (lambda: cu_cluster(55, config_id=26), 7, 0.3, 0.4, 64),
     "cu55_p2": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 2),
     "cu55_p3": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 3),
+    "graph300_grad": (lambda: random_graph(300, config_id=32), 9, 0.5, 0.2, 41),
 }
 
 

@@ -3,7 +3,7 @@
 import numpy as np
 import pytest
 
-from workloads import cu_cluster, rademacher, simple_cubic
+from workloads import cu_cluster, rademacher, random_graph, simple_cubic
 from workloads.cluster import fcc_sphere
 
 
@@ -88,3 +88,18 @@ def test_cu_mu_matches_its_derivation():
     d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "cu_mu.json")))
     assert CU_MU == d["mu_eV"]
     assert abs(d["electrons_per_atom_at_mu"] - 11.0) < 0.01
+
+
+def test_random_graph_structure():
+    H = random_graph(300, config_id=32)
+    A = H.to_scipy()
+    assert abs(A - A.T).max() == 0.0
+    d = np.diff(H.row_ptr)
+    assert d.min() == 1 and d.max() > 8          # a lone diagonal and rows past one gather chunk
+    assert d[H.meta["isolated"]] == 1
+    for i in range(H.n_block_rows):
+        c = H.col_idx[H.row_ptr[i]:H.row_ptr[i + 1]]
+        assert np.all(np.diff(c) > 0) and i in c
+    ev = np.linalg.eigvalsh(A.toarray())
+    assert H.e_min < ev.min() and ev.max() < H.e_max
+    assert random_graph(300, config_id=32).digest() == H.digest()

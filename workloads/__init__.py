@@ -14,6 +14,7 @@ Random streams follow one convention: numpy PCG64 seeded with
 
 from .bsr import BSR
 from .lattice import simple_cubic
+from .graph import random_graph
 from .cluster import CuCluster, cu_cluster
 from .probes import rademacher, identity_probes
 from .configs import CONFIGS, get_config
@@ -21,6 +22,7 @@ from .configs import CONFIGS, get_config
 __all__ = [
     "BSR",
     "simple_cubic",
+    "random_graph",
     "CuCluster",
     "cu_cluster",
     "rademacher",
