@@ -132,7 +132,6 @@ struct Plan {
   int rows_per_wg; // block rows per workgroup
   int n_rg;        // row groups
   int ring;        // moment ring depth
-  int nt;          // non-temporal hints on streamed arrays
   int rpi;         // rows per wave iteration
   int grid;        // resident workgroups of the step kernels
   int n_pt_step;   // probe tiles of the step kernel (BF16: tiles of 16 * ntiles probes)
@@ -164,8 +163,6 @@ Plan make_plan(const rfo_ctx *c) {
   pl.rows_per_wg = (int)rows;
   pl.n_rg = (int)((c->nb + rows - 1) / rows);
   pl.ring = 32;
-  pl.nt = 1;
-  if (const char *env = getenv("RFO_NT")) pl.nt = atoi(env);
   // 1x1 blocks: rows per wave iteration; 9x9 blocks: blocks per gather chunk
   pl.rpi = c->bd == 1 ? 1 : 2;
   if (const char *env = getenv("RFO_RPI")) pl.rpi = atoi(env);
@@ -181,13 +178,14 @@ Plan make_plan(const rfo_ctx *c) {
     }
     pl.n_pt_step = c->sp / (16 * pl.ntiles);
     if (pl.ntiles == 16) pl.rpi = 1;
-    occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi, pl.nt));
+    occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi));
   } else {
-    occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi,
-                                              pl.nt));
+    occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi));
   }
-  // one resident wave of workgroups, a multiple of 8 (one share per XCD)
-  int64_t grid = (int64_t)c->cus * occ;
+  // one resident wave of workgroups, a multiple of 8 (one share per XCD), at
+  // most four per CU: more workgroups widen the band of rows in flight on an XCD
+  // past what its L2 holds of their neighbour rows (measured slower)
+  int64_t grid = (int64_t)c->cus * std::min(occ, 4);
   if (const char *env = getenv("RFO_GRID")) grid = std::max<int64_t>(8, atoll(env));
   const int64_t units = (int64_t)pl.n_pt_step * pl.n_rg;
   grid = std::min(grid, (units + 7) / 8 * 8);
@@ -209,7 +207,6 @@ void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
   a.rows_per_wg = pl.rows_per_wg;
   a.n_rg = pl.n_rg;
   a.n_pt = pl.n_pt_step;
-  a.nt = pl.nt;
   a.rpi = pl.rpi;
   a.grid = pl.grid;
 }

@@ -15,6 +15,31 @@ __device__ __forceinline__ int xcd_logical(int b, int nwg) {
   return xcd < rem ? xcd * (per + 1) + idx : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
+// Persistent schedule of the step kernels over n_pt * n_rg units (probe tile
+// pt, row group rg), tile-major.  Workgroup b runs on XCD x = b mod 8; XCD x
+// owns the contiguous units [U x/8, U (x+1)/8) and its G/8 workgroups sweep
+// them together (unit lo + b/8 + i G/8 at sweep i), so the rows in flight on an
+// XCD form a narrow band that moves through the matrix and the neighbour rows
+// it gathers are still in that XCD's L2.  A workgroup meets the tiles in
+// increasing order, but with a stride above the units per tile it may skip
+// some.
+struct Sched {
+  int64_t i, hi, n_rg;
+  int stride;
+  __device__ Sched(int n_pt, int64_t n_rg_) : n_rg(n_rg_) {
+    const int b = blockIdx.x, G = gridDim.x;
+    const int x = b & 7;
+    const int64_t U = (int64_t)n_pt * n_rg;
+    stride = G >> 3;
+    i = U * x / 8 + (b >> 3);
+    hi = U * (x + 1) / 8;
+  }
+  __device__ bool more() const { return i < hi; }
+  __device__ void next() { i += stride; }
+  __device__ int pt() const { return (int)(i / n_rg); }
+  __device__ int64_t rg() const { return i - (int64_t)pt() * n_rg; }
+};
+
 template <typename T, int N>
 struct alignas(sizeof(T) * N) VecN {
   T v[N];

@@ -32,22 +32,9 @@ __device__ __forceinline__ short bf16_bits(float f) {
   return __builtin_bit_cast(short, b);
 }
 
-struct Sched2 {
-  int64_t u, hi;
-  int stride;
-  __device__ Sched2(int64_t U) {
-    const int b = blockIdx.x, G = gridDim.x;
-    const int x = b & 7;
-    stride = G >> 3;
-    const int64_t lo = U * x / 8;
-    hi = U * (x + 1) / 8;
-    u = lo + (b >> 3);
-  }
-};
-
 }  // namespace
 
-template <int NT, int U, bool NTH>
+template <int NT, int U, bool NTH, bool ACC>
 __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   constexpr int TW = 16 * NT;  // probes per wave (tile width)
   const int wave = uniform(threadIdx.x >> 6);
@@ -65,7 +52,8 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   const bool mom_on = a.part != nullptr;
   const bool need_r = add_r || mom_on;
   const double beta = add_r ? sld(a.beta) : 0.0;
-  const int m = acc ? a.acc_terms : 0;
+  // accumulator terms of this pass (the ACC = false variants carry no code for it)
+  const int m = ACC ? a.acc_terms : 0;
   float al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (float)sld(a.alpha + i) : 0.f;
@@ -76,7 +64,12 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   double mom[NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) mom[t] = 0.0;
-  int first_pt = -1, cur_pt = -1;
+  int cur_pt = -1;
+  // every tile's partials start at zero (a workgroup may skip tiles); the
+  // tiles it meets are overwritten by flush
+  if (mom_on && wave == 0)
+    for (int t = 0; t < a.n_pt; ++t)
+      for (int c = lane; c < TW; c += 64) prow[(int64_t)t * TW + c] = 0.0;
 
   auto flush = [&](int pt) {
 #pragma unroll
@@ -98,12 +91,11 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
     __syncthreads();
   };
 
-  for (Sched2 sc((int64_t)a.n_pt * a.n_rg); sc.u < sc.hi; sc.u += sc.stride) {
-    const int pt = (int)(sc.u / a.n_rg);
-    const int64_t rg = sc.u - (int64_t)pt * a.n_rg;
+  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+    const int pt = sc.pt();
+    const int64_t rg = sc.rg();
     if (pt != cur_pt) {
       if (mom_on && cur_pt >= 0) flush(cur_pt);
-      if (first_pt < 0) first_pt = pt;
       cur_pt = pt;
     }
     const int cp = pt * TW + n * NT;  // first probe column of this lane
@@ -201,13 +193,6 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   }
   if (mom_on) {
     if (cur_pt >= 0) flush(cur_pt);
-    if (wave == 0) {
-      const int npt = a.n_pt;
-      for (int t = 0; t < npt; ++t) {
-        if (t >= first_pt && t <= cur_pt) continue;
-        for (int c = lane; c < TW; c += 64) prow[(int64_t)t * TW + c] = 0.0;
-      }
-    }
   }
 }
 
@@ -234,10 +219,11 @@ __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hh
 
 namespace {
 
-const void *select_bf16(int nt_tiles, int u, int nth) {
+const void *select_bf16(int nt_tiles, int u, bool acc) {
 #define RFO_BF16_CASE(T, UU)                                                        \
   if (nt_tiles == T && u == UU)                                                     \
-    return nth ? (const void *)k_step9_bf16<T, UU, true> : (const void *)k_step9_bf16<T, UU, false>;
+    return acc ? (const void *)k_step9_bf16<T, UU, true, true>                      \
+               : (const void *)k_step9_bf16<T, UU, true, false>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
   RFO_BF16_CASE(8, 1)
@@ -249,8 +235,8 @@ const void *select_bf16(int nt_tiles, int u, int nth) {
 
 }  // namespace
 
-int step_bf16_blocks_per_cu(int nt_tiles, int u, int nth) {
-  const void *f = select_bf16(nt_tiles, u, nth);
+int step_bf16_blocks_per_cu(int nt_tiles, int u) {
+  const void *f = select_bf16(nt_tiles, u, false);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -258,7 +244,7 @@ int step_bf16_blocks_per_cu(int nt_tiles, int u, int nth) {
 }
 
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s) {
-  const void *f = select_bf16(nt_tiles, a.rpi, a.nt);
+  const void *f = select_bf16(nt_tiles, a.rpi, a.acc != nullptr && a.acc_terms > 0);
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);

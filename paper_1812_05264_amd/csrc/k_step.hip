@@ -13,13 +13,9 @@
 // wave-uniform and come through the scalar cache; each neighbour's vector rows
 // are read as whole coalesced segments.
 //
-// Schedule: the grid is one resident wave of G workgroups (G a multiple of 8).
-// The work is U = n_pt * n_rg units (probe tile, group of rows_per_wg block
-// rows), ordered tile-major.  XCD x (hardware workgroups b with b mod 8 = x)
-// owns the contiguous units [U x/8, U (x+1)/8) and its G/8 workgroups sweep
-// them together, unit lo + b/8 + i G/8 at sweep i.  The rows in flight on an
-// XCD therefore form a narrow band that moves through the matrix, and the
-// neighbour rows it gathers are still in that XCD's L2.
+// Schedule: the grid is one resident wave of G workgroups (G a multiple of 8)
+// sweeping n_pt * n_rg units (probe tile, group of rows_per_wg block rows) in
+// XCD-aware bands (Sched in device_util.h).
 //
 // Moment partials: workgroup b owns row b of a [G][sp] array.  Its units visit
 // the probe tiles in increasing order; when it leaves a tile it sums its four
@@ -32,19 +28,6 @@
 namespace rfo {
 
 namespace {
-
-struct Sched {
-  int64_t u, hi;
-  int stride;
-  __device__ Sched(int64_t U) {
-    const int b = blockIdx.x, G = gridDim.x;
-    const int x = b & 7;
-    stride = G >> 3;
-    const int64_t lo = U * x / 8;
-    hi = U * (x + 1) / 8;
-    u = lo + (b >> 3);
-  }
-};
 
 template <int PPL>
 __device__ __forceinline__ void flush_tile(double (&mom)[PPL], double (*red)[64 * PPL], int wave,
@@ -67,15 +50,15 @@ __device__ __forceinline__ void flush_tile(double (&mom)[PPL], double (*red)[64 
   __syncthreads();
 }
 
+// Zero this workgroup's partial row for every tile before the sweep: the tiles
+// it never meets (with a stride above the units per tile it may skip some)
+// must read as zero, and those it meets are overwritten by flush_tile.
 template <int PPL>
-__device__ __forceinline__ void zero_other_tiles(double *prow, int first, int last, int n_pt,
-                                                 int wave, int lane) {
+__device__ __forceinline__ void zero_partials(double *prow, int n_pt, int wave, int lane) {
   if (wave != 0) return;
-  for (int t = 0; t < n_pt; ++t) {
-    if (t >= first && t <= last) continue;
+  for (int t = 0; t < n_pt; ++t)
 #pragma unroll
     for (int q = 0; q < PPL; ++q) prow[t * (64 * PPL) + lane * PPL + q] = 0.0;
-  }
 }
 
 }  // namespace
@@ -88,7 +71,7 @@ __device__ __forceinline__ void zero_other_tiles(double *prow, int first, int la
 // so a chunk may read past the end of the last row; entries past a row's end
 // get zero weight.  NT selects non-temporal hints for the streamed arrays.
 // ---------------------------------------------------------------------------
-template <typename VT, typename MT, int PPL, int U, int RPI, bool NT>
+template <typename VT, typename MT, int PPL, int U, int RPI, bool NT, bool ACC>
 __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -104,7 +87,8 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const bool mom_on = a.part != nullptr;
   const bool need_r = add_r || mom_on;
   const double beta = add_r ? sld(a.beta) : 0.0;
-  const int m = acc ? a.acc_terms : 0;
+  // accumulator terms of this pass (the ACC = false variants carry no code for it)
+  const int m = ACC ? a.acc_terms : 0;
   VT al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
@@ -115,14 +99,14 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   double mom[PPL];
 #pragma unroll
   for (int q = 0; q < PPL; ++q) mom[q] = 0.0;
-  int first_pt = -1, cur_pt = -1;
+  int cur_pt = -1;
+  if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
 
-  for (Sched sc((int64_t)a.n_pt * a.n_rg); sc.u < sc.hi; sc.u += sc.stride) {
-    const int pt = (int)(sc.u / a.n_rg);
-    const int64_t rg = sc.u - (int64_t)pt * a.n_rg;
+  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+    const int pt = sc.pt();
+    const int64_t rg = sc.rg();
     if (pt != cur_pt) {
       if (mom_on && cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
-      if (first_pt < 0) first_pt = pt;
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
@@ -143,7 +127,6 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
       for (int r = 0; r < RPI; ++r) {
         const int64_t off = Ir[r] * sp + c0;
         if (has_prev) pv[r] = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
-        if (m >= 2) xs[r] = ldv<VT, PPL>(x + off);
         if (need_r) {
           if (a.sgn) sw[r] = a.sgn[Ir[r] * nw + (c0 >> 6)];
           else rv[r] = ldv<double, PPL>(a.rden + off);
@@ -177,6 +160,9 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
             const VT h = nz < end[r] ? (VT)sld(hval + nz) : (VT)0;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) s[r][q] = fma(h, xv[r][u].v[q], s[r][q]);
+            // y_k of the row itself for the accumulator: every row stores its
+            // diagonal, so one of the gathered rows is it
+            if (m >= 2 && J[r][u] == Ir[r]) xs[r] = xv[r][u];
           }
       }
 #pragma unroll
@@ -197,6 +183,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
             const VT h = nz < end[r] ? (VT)sld(hval + nz) : (VT)0;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) s[r][q] = fma(h, xv[u].v[q], s[r][q]);
+            if (m >= 2 && J[u] == Ir[r]) xs[r] = xv[u];
           }
         }
       }
@@ -228,7 +215,6 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   }
   if (mom_on) {
     if (cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
-    zero_other_tiles<PPL>(prow, first_pt, cur_pt, a.n_pt, wave, lane);
   }
 }
 
@@ -240,7 +226,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
 // through the scalar cache instead serializes: sixteen waves per CU on
 // different block rows overflow it.)
 // ---------------------------------------------------------------------------
-template <typename VT, typename MT, int PPL, int U, bool NT>
+template <typename VT, typename MT, int PPL, int U, bool NT, bool ACC>
 __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   constexpr int BD = 9, BB = 81;
   constexpr int CH = U * BB;                       // H_hat values per chunk
@@ -258,7 +244,8 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   const bool mom_on = a.part != nullptr;
   const bool need_r = add_r || mom_on;
   const double beta = add_r ? sld(a.beta) : 0.0;
-  const int m = acc ? a.acc_terms : 0;
+  // accumulator terms of this pass (the ACC = false variants carry no code for it)
+  const int m = ACC ? a.acc_terms : 0;
   VT al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
@@ -271,14 +258,14 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   double mom[PPL];
 #pragma unroll
   for (int q = 0; q < PPL; ++q) mom[q] = 0.0;
-  int first_pt = -1, cur_pt = -1;
+  int cur_pt = -1;
+  if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
 
-  for (Sched sc((int64_t)a.n_pt * a.n_rg); sc.u < sc.hi; sc.u += sc.stride) {
-    const int pt = (int)(sc.u / a.n_rg);
-    const int64_t rg = sc.u - (int64_t)pt * a.n_rg;
+  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+    const int pt = sc.pt();
+    const int64_t rg = sc.rg();
     if (pt != cur_pt) {
       if (mom_on && cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
-      if (first_pt < 0) first_pt = pt;
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
@@ -291,26 +278,28 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
       for (int i = 0; i < BD; ++i)
 #pragma unroll
         for (int q = 0; q < PPL; ++q) s[i][q] = (VT)0;
-      for (int64_t nz = beg; nz < end; nz += U) {
-        // H_hat chunk -> registers (coalesced), neighbour gathers, then LDS
-        MT hv[(CH + 63) / 64];
+      constexpr int NH = (CH + 63) / 64;
+      // H_hat chunk -> registers (coalesced) and the neighbour gathers
+      auto load_chunk = [&](int64_t nz, MT(&hv)[NH], VecN<VT, PPL>(&xv)[U][BD]) {
         const MT *hsrc = hval + nz * BB;
 #pragma unroll
-        for (int k = 0; k < (CH + 63) / 64; ++k) {
+        for (int k = 0; k < NH; ++k) {
           const int e = k * 64 + lane;
           if (e < CH) hv[k] = hsrc[e];
         }
         int64_t J[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) J[u] = sld(a.col + nz + u);
-        VecN<VT, PPL> xv[U][BD];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
           for (int j = 0; j < BD; ++j) xv[u][j] = ldv<VT, PPL>(x + (J[u] * BD + j) * sp + c0);
+      };
+      // H_hat chunk -> LDS, then the FMAs with LDS broadcasts
+      auto use_chunk = [&](int64_t nz, const MT(&hv)[NH], const VecN<VT, PPL>(&xv)[U][BD]) {
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int k = 0; k < (CH + 63) / 64; ++k) {
+        for (int k = 0; k < NH; ++k) {
           const int e = k * 64 + lane;
           if (e < CH) hw[e] = hv[k];
         }
@@ -330,6 +319,12 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
               }
           }
         }
+      };
+      for (int64_t nz = beg; nz < end; nz += U) {
+        MT hv[NH];
+        VecN<VT, PPL> xv[U][BD];
+        load_chunk(nz, hv, xv);
+        use_chunk(nz, hv, xv);
       }
 #pragma unroll
       for (int i = 0; i < BD; ++i) {
@@ -372,7 +367,6 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   }
   if (mom_on) {
     if (cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
-    zero_other_tiles<PPL>(prow, first_pt, cur_pt, a.n_pt, wave, lane);
   }
 }
 
@@ -395,13 +389,13 @@ __global__ __launch_bounds__(kWG) void k_init(InitArgs a) {
   double mom[PPL];
 #pragma unroll
   for (int q = 0; q < PPL; ++q) mom[q] = 0.0;
-  int first_pt = -1, cur_pt = -1;
-  for (Sched sc((int64_t)a.n_pt * a.n_rg); sc.u < sc.hi; sc.u += sc.stride) {
-    const int pt = (int)(sc.u / a.n_rg);
-    const int64_t rg = sc.u - (int64_t)pt * a.n_rg;
+  int cur_pt = -1;
+  if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
+  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+    const int pt = sc.pt();
+    const int64_t rg = sc.rg();
     if (pt != cur_pt) {
       if (mom_on && cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
-      if (first_pt < 0) first_pt = pt;
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
@@ -426,7 +420,6 @@ __global__ __launch_bounds__(kWG) void k_init(InitArgs a) {
   }
   if (mom_on) {
     if (cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
-    zero_other_tiles<PPL>(prow, first_pt, cur_pt, a.n_pt, wave, lane);
   }
 }
 
@@ -435,34 +428,31 @@ __global__ __launch_bounds__(kWG) void k_init(InitArgs a) {
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename VT, typename MT, int PPL>
-const void *step_fn(int bd, int rpi, int nt) {
-  if (bd == 1) {
-    if (rpi == 2)
-      return nt ? (const void *)k_step1<VT, MT, PPL, 8, 2, true>
-                : (const void *)k_step1<VT, MT, PPL, 8, 2, false>;
-    return nt ? (const void *)k_step1<VT, MT, PPL, 8, 1, true>
-              : (const void *)k_step1<VT, MT, PPL, 8, 1, false>;
-  }
-  if (rpi == 1)
-    return nt ? (const void *)k_step9<VT, MT, PPL, 1, true> : (const void *)k_step9<VT, MT, PPL, 1, false>;
-  return nt ? (const void *)k_step9<VT, MT, PPL, 2, true> : (const void *)k_step9<VT, MT, PPL, 2, false>;
+template <typename VT, typename MT, int PPL, bool ACC>
+const void *step_fn(int bd, int rpi) {
+  // 1x1: rpi = rows per wave iteration; 9x9: rpi = blocks per gather chunk
+  if (bd == 1)
+    return rpi == 2 ? (const void *)k_step1<VT, MT, PPL, 8, 2, true, ACC>
+                    : (const void *)k_step1<VT, MT, PPL, 8, 1, true, ACC>;
+  return rpi == 2 ? (const void *)k_step9<VT, MT, PPL, 2, true, ACC>
+                  : (const void *)k_step9<VT, MT, PPL, 1, true, ACC>;
 }
 
-template <typename VT, typename MT>
-const void *step_fn_t(int bd, int ppl, int rpi, int nt) {
+template <typename VT, typename MT, bool ACC>
+const void *step_fn_t(int bd, int ppl, int rpi) {
   switch (ppl) {
-    case 1: return step_fn<VT, MT, 1>(bd, rpi, nt);
-    case 2: return step_fn<VT, MT, 2>(bd, rpi, nt);
-    case 4: return step_fn<VT, MT, 4>(bd, rpi, nt);
+    case 1: return step_fn<VT, MT, 1, ACC>(bd, rpi);
+    case 2: return step_fn<VT, MT, 2, ACC>(bd, rpi);
+    case 4: return step_fn<VT, MT, 4, ACC>(bd, rpi);
     default: return nullptr;
   }
 }
 
-const void *select_step(int bd, int precision, int ppl, int rpi, int nt) {
-  if (bd != 1 && bd != 9) return nullptr;
-  return precision == 0 ? step_fn_t<double, double>(bd, ppl, rpi, nt)
-                        : step_fn_t<float, float>(bd, ppl, rpi, nt);
+const void *select_step(int bd, int precision, int ppl, int rpi, bool acc) {
+  if ((bd != 1 && bd != 9) || rpi < 1 || rpi > 2) return nullptr;
+  if (precision == 0)
+    return acc ? step_fn_t<double, double, true>(bd, ppl, rpi) : step_fn_t<double, double, false>(bd, ppl, rpi);
+  return acc ? step_fn_t<float, float, true>(bd, ppl, rpi) : step_fn_t<float, float, false>(bd, ppl, rpi);
 }
 
 const void *select_init(int precision, int ppl) {
@@ -484,8 +474,8 @@ const void *select_init(int precision, int ppl) {
 
 }  // namespace
 
-int step_blocks_per_cu(int bd, int precision, int ppl, int rpi, int nt) {
-  const void *f = select_step(bd, precision, ppl, rpi, nt);
+int step_blocks_per_cu(int bd, int precision, int ppl, int rpi) {
+  const void *f = select_step(bd, precision, ppl, rpi, false);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -493,7 +483,7 @@ int step_blocks_per_cu(int bd, int precision, int ppl, int rpi, int nt) {
 }
 
 hipError_t launch_step(int bd, int precision, int ppl, const StepArgs &a, hipStream_t s) {
-  const void *f = select_step(bd, precision, ppl, a.rpi, a.nt);
+  const void *f = select_step(bd, precision, ppl, a.rpi, a.acc != nullptr && a.acc_terms > 0);
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);

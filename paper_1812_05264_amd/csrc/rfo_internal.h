@@ -43,7 +43,6 @@ struct StepArgs {
   int sp;
   int rows_per_wg;
   int n_rg, n_pt;
-  int nt;                  // non-temporal hints on the streamed arrays
   int rpi;                 // rows per wave iteration (1x1 blocks: 1 or 2)
   int grid;                // workgroups (multiple of 8); part has [grid][sp]
 };
@@ -70,11 +69,11 @@ struct InitArgs {
 };
 hipError_t launch_init(int precision, const InitArgs &a, hipStream_t s);
 // Resident workgroups per CU of the step kernel variant (0 on error).
-int step_blocks_per_cu(int bd, int precision, int ppl, int rpi, int nt);
+int step_blocks_per_cu(int bd, int precision, int ppl, int rpi);
 // BF16 MFMA step for 9x9 blocks; a.hval holds the packed A operands
 // ([nnzb + kStepPad][27] uint2), a.n_pt counts tiles of 16 * nt_tiles probes.
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s);
-int step_bf16_blocks_per_cu(int nt_tiles, int u, int nth);  // u = blocks per chunk (a.rpi)
+int step_bf16_blocks_per_cu(int nt_tiles, int u);  // u = blocks per chunk (a.rpi)
 hipError_t launch_pack_bf16(const double *hhat, void *hpack, int64_t nnzb, hipStream_t s);
 
 // ---------------------------------------------------------------------------

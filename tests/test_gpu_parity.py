@@ -25,6 +25,9 @@ CASES = {
     "cu201": (lambda: cu_cluster(201, config_id=23).bsr(), 128, 0.2, 0.1, 160),
     # uneven rows (1 to 26 entries, one isolated site): the general row layout
     "graph700_uneven": (lambda: random_graph(700, config_id=31), 136, 0.5, 0.3, 150),
+    # few rows, many probe tiles: workgroups stride over whole tiles
+    "sc3_many_tiles": (lambda: simple_cubic(3, disorder=0.4, config_id=27), 1100, 0.3, 0.1, 40),
+    "cu13_many_tiles": (lambda: cu_cluster(13, config_id=28).bsr(), 1000, 0.3, 0.1, 40),
 }
 
 

@@ -39,7 +39,7 @@ def test_fp32_against_oracle(name, build, s, T, mu, p):
 
 
 @pytest.mark.parametrize("name,atoms,s,p", [("cu55_s64", 55, 64, 120), ("cu201_s100", 201, 100, 120),
-                                            ("cu201_s256", 201, 256, 80)])
+                                            ("cu201_s256", 201, 256, 80), ("cu13_s1000", 13, 1000, 40)])
 def test_bf16_mfma_against_oracle(name, atoms, s, p):
     banner(f"bf16 {name}")
     eng = engine_or_skip()
