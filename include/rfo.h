@@ -115,6 +115,10 @@ int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R,
  *   NEF_out     [3]     N, E, F (nullable)
  *   density_out [nnzb][bd][bd]  M (.) P~, unsymmetrized (nullable; when NULL
  *               the density accumulator is not run)
+ * Without density and with moment doubling on (the default), the moments come
+ * from floor(p/2) steps instead: mu_2j = 2 y_j.y_j - mu_0 and
+ * mu_2j-1 = 2 y_j.y_j-1 - mu_1 (T_2j = 2 T_j^2 - T_0, T_2j-1 = 2 T_j T_j-1 - T_1),
+ * the same values up to rounding.
  * Requires T > 0, finite mu, 1 <= n_terms <= 1048576.
  * Errors: RFO_E_STATE without H or probes; RFO_E_NUMERIC when a moment
  * exceeds ||r_c||^2 (relative slack 1e-6 in FP64, 1e-3 in FP32/BF16). */
@@ -140,6 +144,11 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
  *   forces_out [n_block_rows][3].
  * Errors: RFO_E_STATE before rfo_energy_and_dEdH. */
 int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out);
+
+/* Moment doubling for calls without density output (see rfo_fermi_moments):
+ * enabled != 0 turns it on (the default), 0 makes every moment a direct
+ * r . y_k over p - 1 steps. */
+int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
 
 /* Instrumentation: when enabled, the library records HIP events around each
  * run of consecutive Chebyshev-step launches on its stream.  rfo_step_timing

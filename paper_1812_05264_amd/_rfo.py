@@ -54,10 +54,11 @@ def load():
     lib.rfo_energy_and_dEdH.argtypes = [vp, dbl, dbl, i64, vp, vp]
     lib.rfo_hf_forces.argtypes = [vp, vp, vp]
     lib.rfo_set_timing.argtypes = [vp, i32]
+    lib.rfo_set_moment_doubling.argtypes = [vp, i32]
     lib.rfo_step_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for f in ("rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
               "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing",
-              "rfo_step_timing"):
+              "rfo_step_timing", "rfo_set_moment_doubling"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -199,6 +200,10 @@ class Engine:
         return out
 
     # -- instrumentation --------------------------------------------------------------
+    def set_moment_doubling(self, enabled=True):
+        """Moment-only fermi_moments calls run floor(p/2) steps (doubling identities)."""
+        self._check(self._lib.rfo_set_moment_doubling(self._ctx, 1 if enabled else 0))
+
     def set_timing(self, enabled=True):
         self._check(self._lib.rfo_set_timing(self._ctx, 1 if enabled else 0))
 

@@ -50,6 +50,8 @@ struct rfo_ctx {
   DevBuf vec, acc, ring, moments, coef, samples, costab, small, flags, G, dHdR, forces;
   bool has_grad = false;
 
+  bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
+
   // instrumentation
   bool timing = false;
   double t_ms = 0.0;
@@ -287,7 +289,8 @@ struct Checkpoints {
 };
 
 int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_acc,
-                const Checkpoints *ck, size_t *n_events) {
+                const Checkpoints *ck, size_t *n_events, bool dbl = false) {
+  if (dbl && (use_acc || ck)) return fail(ctx, RFO_E_INVALID, "doubling moments need all y_k");
   const int kp = kernel_precision(ctx);
   const double tol = ctx->prec == RFO_FP64 ? 1e-6 : (ctx->prec == RFO_FP32 ? 1e-3 : 1e-2);
   const size_t slot = (size_t)pl.grid * ctx->sp;
@@ -323,18 +326,23 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
   ia.alpha = coef;  // alpha^f_0
   ia.part = ring;
   HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
-  HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, 0, 1, pl.grid, ctx->sp, mom, 0, tol, flags,
+  HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, 0, 1, pl.grid, ctx->sp, mom, 0, tol, flags, 0,
                                    ctx->stream));
   TRY(save(0, A));
 
   rfo::StepArgs sa;
   fill_step(ctx, pl, sa);
   char *cur = A, *prev = B;
-  int64_t batch_start = 1;
-  int64_t acc_done = 0;  // the accumulator holds alpha_j y_j for j <= acc_done
+  // direct: step k makes y_{k+1} and moment k+1 = r . y_{k+1} (p - 1 steps);
+  // doubling: step k makes y_j (j = k+1) and the inner products that give
+  // moments 2j-1 and 2j, so floor(p/2) steps reach moment p-1
+  const int64_t n_steps = dbl ? p / 2 : p - 1;
+  int64_t batch_start = 1;  // first moment index not yet reduced
+  int64_t batch_steps = 0;
+  int64_t acc_done = 0;     // the accumulator holds alpha_j y_j for j <= acc_done
   size_t ev = 0;
-  for (int64_t k = 0; k + 1 < p; ++k) {
-    if (ctx->timing && k + 1 == batch_start) {
+  for (int64_t k = 0; k < n_steps; ++k) {
+    if (ctx->timing && batch_steps == 0) {
       hipEvent_t e = next_event(ctx, ev++);
       if (!e) return fail(ctx, RFO_E_DEVICE, "hipEventCreate failed");
       HIPCHK(hipEventRecord(e, ctx->stream));
@@ -353,24 +361,31 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
     sa.acc_terms = (accp && (pending == 3 || k + 2 == p)) ? (int)pending : 0;
     sa.alpha = coef + (acc_done + 1);
     if (sa.acc_terms) acc_done = k + 1;
-    sa.part = ring + (size_t)((k + 1) % pl.ring) * slot;
+    const int64_t hi = dbl ? 2 * (k + 1) : k + 1;  // highest moment index of this step
+    sa.part = ring + (size_t)(hi % pl.ring) * slot;
+    sa.part2 = dbl ? ring + (size_t)((hi - 1) % pl.ring) * slot : nullptr;
     HIPCHK(launch_any_step(ctx, pl, sa));
     prev = cur;
     cur = out;
-    const int64_t idx = k + 1;
-    const bool flush = (idx - batch_start + 1 == pl.ring) || (idx == p - 1);
+    ++batch_steps;
+    const int64_t next_hi = hi + (dbl ? 2 : 1);
+    // moments 0 and 1 must be final before a doubling reduction uses them
+    const bool flush = (k + 1 == n_steps) || (dbl && k == 0) || (next_hi - batch_start + 1 > pl.ring);
     if (flush) {
       if (ctx->timing) {
         hipEvent_t e = next_event(ctx, ev++);
         if (!e) return fail(ctx, RFO_E_DEVICE, "hipEventCreate failed");
         HIPCHK(hipEventRecord(e, ctx->stream));
-        ctx->t_steps += idx - batch_start + 1;
+        ctx->t_steps += batch_steps;
       }
-      HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, batch_start, (int)(idx - batch_start + 1),
-                                       pl.grid, ctx->sp, mom, 1, tol, flags, ctx->stream));
-      batch_start = idx + 1;
+      const int64_t last = std::min(hi, p - 1);
+      HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, batch_start, (int)(last - batch_start + 1),
+                                       pl.grid, ctx->sp, mom, 1, tol, flags, dbl ? 1 : 0,
+                                       ctx->stream));
+      batch_start = last + 1;
+      batch_steps = 0;
     }
-    TRY(save(idx, cur));
+    TRY(save(k + 1, cur));
   }
   *n_events = ev;
   return RFO_OK;
@@ -664,7 +679,7 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
   TRY(ensure(ctx, ctx->vec, 2 * pl.vec_elems * pl.vt_bytes));
   if (dens) TRY(ensure(ctx, ctx->acc, pl.vec_elems * pl.vt_bytes));
   size_t n_events = 0;
-  TRY(run_forward(ctx, pl, n_terms, ctx->vec, dens, nullptr, &n_events));
+  TRY(run_forward(ctx, pl, n_terms, ctx->vec, dens, nullptr, &n_events, !dens && ctx->doubling));
   double *obs = P<double>(ctx->small);
   HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef),
                             n_terms, ctx->sp, obs, ctx->stream));
@@ -854,6 +869,13 @@ int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out) {
                             ctx->stream));
   TRY(copy_out(ctx, forces_out, ctx->forces.p, (size_t)ctx->nb * 3 * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  ctx->doubling = enabled != 0;
   return RFO_OK;
 }
 

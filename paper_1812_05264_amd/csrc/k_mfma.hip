@@ -34,7 +34,7 @@ __device__ __forceinline__ short bf16_bits(float f) {
 
 }  // namespace
 
-template <int NT, int U, bool NTH, bool ACC>
+template <int NT, int U, bool NTH, int MODE>
 __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   constexpr int TW = 16 * NT;  // probes per wave (tile width)
   const int wave = uniform(threadIdx.x >> 6);
@@ -50,10 +50,12 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   const bool has_prev = a.c2 != 0.0;
   const bool add_r = a.beta != nullptr;
   const bool mom_on = a.part != nullptr;
-  const bool need_r = add_r || mom_on;
+  // MODE 1: density accumulator terms; MODE 2: doubling moments <y,y>, <y,y_k>
+  // instead of r.y (the MODE 0 variants carry no code for either)
+  constexpr bool DBL = MODE == 2;
+  const bool need_r = add_r || (mom_on && !DBL);
   const double beta = add_r ? sld(a.beta) : 0.0;
-  // accumulator terms of this pass (the ACC = false variants carry no code for it)
-  const int m = ACC ? a.acc_terms : 0;
+  const int m = MODE == 1 ? a.acc_terms : 0;
   float al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (float)sld(a.alpha + i) : 0.f;
@@ -61,21 +63,25 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   __shared__ double red[kWaves][4][TW];
   double *prow = mom_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
 
-  double mom[NT];
+  double mom[NT], mom2[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) mom[t] = 0.0;
+  for (int t = 0; t < NT; ++t) mom[t] = mom2[t] = 0.0;
   int cur_pt = -1;
+  double *prow2 = DBL && mom_on ? a.part2 + (int64_t)blockIdx.x * sp : nullptr;
   // every tile's partials start at zero (a workgroup may skip tiles); the
   // tiles it meets are overwritten by flush
   if (mom_on && wave == 0)
     for (int t = 0; t < a.n_pt; ++t)
-      for (int c = lane; c < TW; c += 64) prow[(int64_t)t * TW + c] = 0.0;
+      for (int c = lane; c < TW; c += 64) {
+        prow[(int64_t)t * TW + c] = 0.0;
+        if (DBL) prow2[(int64_t)t * TW + c] = 0.0;
+      }
 
-  auto flush = [&](int pt) {
+  auto flush1 = [&](double(&mm)[NT], double *dst, int pt) {
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
-      red[wave][g][n * NT + t] = mom[t];
-      mom[t] = 0.0;
+      red[wave][g][n * NT + t] = mm[t];
+      mm[t] = 0.0;
     }
     __syncthreads();
     if (wave == 0) {
@@ -85,10 +91,14 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
         for (int w = 0; w < kWaves; ++w)
 #pragma unroll
           for (int gg = 0; gg < 4; ++gg) s += red[w][gg][c];
-        prow[(int64_t)pt * TW + c] = s;
+        dst[(int64_t)pt * TW + c] = s;
       }
     }
     __syncthreads();
+  };
+  auto flush = [&](int pt) {
+    flush1(mom, prow, pt);
+    if (DBL) flush1(mom2, prow2, pt);
   };
 
   for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
@@ -156,7 +166,7 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
         const int64_t row = I * 9 + min(4 * g + i, 8);
         if (has_prev) pv4[i] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
                                    : ldv<float, NT>(prev + row * sp + cp);
-        if (m >= 2) xs4[i] = ldv<float, NT>(x + row * sp + cp);
+        if (m >= 2 || DBL) xs4[i] = ldv<float, NT>(x + row * sp + cp);
         if (need_r && a.sgn) sw4[i] = a.sgn[row * nw + (cp >> 6)];
       }
 #pragma unroll
@@ -178,7 +188,14 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
           if (has_prev) v = fmaf(c2, pv.v[t], v);
           if (add_r) v = (float)((double)v + beta * rq);
           o.v[t] = v;
-          if (mom_on) mom[t] = fma(rq, (double)v, mom[t]);
+          if (mom_on) {
+            if (DBL) {
+              mom[t] = fma((double)v, (double)v, mom[t]);
+              mom2[t] = fma((double)v, (double)xs4[i].v[t], mom2[t]);
+            } else {
+              mom[t] = fma(rq, (double)v, mom[t]);
+            }
+          }
         }
         if (NTH) stv_nt<float, NT>(out + off, o);
         else stv<float, NT>(out + off, o);
@@ -219,11 +236,12 @@ __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hh
 
 namespace {
 
-const void *select_bf16(int nt_tiles, int u, bool acc) {
+const void *select_bf16(int nt_tiles, int u, int mode) {
 #define RFO_BF16_CASE(T, UU)                                                        \
   if (nt_tiles == T && u == UU)                                                     \
-    return acc ? (const void *)k_step9_bf16<T, UU, true, true>                      \
-               : (const void *)k_step9_bf16<T, UU, true, false>;
+    return mode == 1 ? (const void *)k_step9_bf16<T, UU, true, 1>                   \
+                     : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2>       \
+                                 : (const void *)k_step9_bf16<T, UU, true, 0>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
   RFO_BF16_CASE(8, 1)
@@ -236,7 +254,7 @@ const void *select_bf16(int nt_tiles, int u, bool acc) {
 }  // namespace
 
 int step_bf16_blocks_per_cu(int nt_tiles, int u) {
-  const void *f = select_bf16(nt_tiles, u, false);
+  const void *f = select_bf16(nt_tiles, u, 0);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -244,7 +262,7 @@ int step_bf16_blocks_per_cu(int nt_tiles, int u) {
 }
 
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s) {
-  const void *f = select_bf16(nt_tiles, a.rpi, a.acc != nullptr && a.acc_terms > 0);
+  const void *f = select_bf16(nt_tiles, a.rpi, step_mode(a));
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);

@@ -240,7 +240,7 @@ hipError_t launch_coefficients(double e_min, double e_max, double T, double mu, 
 __global__ __launch_bounds__(kWG) void k_moment_reduce(const double *__restrict__ part, int ring,
                                                        int64_t k0, int count, int n_rg, int sp,
                                                        double *__restrict__ moments, int check,
-                                                       double tol, int *flags) {
+                                                       double tol, int *flags, int dbl) {
   const int chunks = sp >> 6;
   const int d = blockIdx.x / chunks;
   const int c = (blockIdx.x - d * chunks) * 64 + (threadIdx.x & 63);
@@ -260,6 +260,9 @@ __global__ __launch_bounds__(kWG) void k_moment_reduce(const double *__restrict_
   if (wave == 0) {
     double sum = red[0][threadIdx.x];
     for (int w = 1; w < kWaves; ++w) sum += red[w][threadIdx.x];
+    // doubling: the partials hold <y_j, y_j> (k = 2j) or <y_j, y_{j-1}> (k = 2j-1);
+    // T_2j = 2 T_j^2 - T_0 and T_2j-1 = 2 T_j T_j-1 - T_1 give the moment
+    if (dbl && k >= 2) sum = 2.0 * sum - moments[(k & 1) * sp + c];
     moments[k * sp + c] = sum;
     if (check) {
       const double bound = moments[c] * (1.0 + tol) + 1e-300;
@@ -270,9 +273,10 @@ __global__ __launch_bounds__(kWG) void k_moment_reduce(const double *__restrict_
 
 hipError_t launch_moment_reduce(const double *part, int ring, int64_t k0, int count, int n_rg,
                                 int sp, double *moments, int check, double tol, int *flags,
-                                hipStream_t s) {
+                                int dbl, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)(count * (sp >> 6))), dim3(kWG), 0, s, part,
-                     ring, k0, count, n_rg, sp, moments, check, tol, flags);
+                     ring, k0, count, n_rg, sp, moments, check, tol, flags, dbl);
   return hipGetLastError();
 }
 

@@ -71,7 +71,7 @@ __device__ __forceinline__ void zero_partials(double *prow, int n_pt, int wave, 
 // so a chunk may read past the end of the last row; entries past a row's end
 // get zero weight.  NT selects non-temporal hints for the streamed arrays.
 // ---------------------------------------------------------------------------
-template <typename VT, typename MT, int PPL, int U, int RPI, bool NT, bool ACC>
+template <typename VT, typename MT, int PPL, int U, int RPI, bool NT, int MODE>
 __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -85,10 +85,12 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const bool has_prev = a.c2 != 0.0;
   const bool add_r = a.beta != nullptr;
   const bool mom_on = a.part != nullptr;
-  const bool need_r = add_r || mom_on;
+  // MODE 1: density accumulator terms; MODE 2: doubling moments <y,y>, <y,y_k>
+  // instead of r.y (the MODE 0 variants carry no code for either)
+  constexpr bool DBL = MODE == 2;
+  const bool need_r = add_r || (mom_on && !DBL);
   const double beta = add_r ? sld(a.beta) : 0.0;
-  // accumulator terms of this pass (the ACC = false variants carry no code for it)
-  const int m = ACC ? a.acc_terms : 0;
+  const int m = MODE == 1 ? a.acc_terms : 0;
   VT al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
@@ -96,17 +98,22 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   __shared__ double red[kWaves][64 * PPL];
   double *prow = mom_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
 
-  double mom[PPL];
+  double mom[PPL], mom2[PPL];
 #pragma unroll
-  for (int q = 0; q < PPL; ++q) mom[q] = 0.0;
+  for (int q = 0; q < PPL; ++q) mom[q] = mom2[q] = 0.0;
   int cur_pt = -1;
+  double *prow2 = DBL && mom_on ? a.part2 + (int64_t)blockIdx.x * sp : nullptr;
   if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
+  if (DBL && mom_on) zero_partials<PPL>(prow2, a.n_pt, wave, lane);
 
   for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
     const int pt = sc.pt();
     const int64_t rg = sc.rg();
     if (pt != cur_pt) {
-      if (mom_on && cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+      if (mom_on && cur_pt >= 0) {
+        flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+        if (DBL) flush_tile<PPL>(mom2, red, wave, lane, prow2, cur_pt);
+      }
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
@@ -162,7 +169,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
             for (int q = 0; q < PPL; ++q) s[r][q] = fma(h, xv[r][u].v[q], s[r][q]);
             // y_k of the row itself for the accumulator: every row stores its
             // diagonal, so one of the gathered rows is it
-            if (m >= 2 && J[r][u] == Ir[r]) xs[r] = xv[r][u];
+            if ((m >= 2 || DBL) && J[r][u] == Ir[r]) xs[r] = xv[r][u];
           }
       }
 #pragma unroll
@@ -183,7 +190,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
             const VT h = nz < end[r] ? (VT)sld(hval + nz) : (VT)0;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) s[r][q] = fma(h, xv[u].v[q], s[r][q]);
-            if (m >= 2 && J[u] == Ir[r]) xs[r] = xv[u];
+            if ((m >= 2 || DBL) && J[u] == Ir[r]) xs[r] = xv[u];
           }
         }
       }
@@ -200,7 +207,14 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
           if (has_prev) v = fma(c2, pv[r].v[q], v);
           if (add_r) v = (VT)((double)v + beta * rq);
           o.v[q] = v;
-          if (mom_on) mom[q] = fma(rq, (double)v, mom[q]);
+          if (mom_on) {
+            if (DBL) {
+              mom[q] = fma((double)v, (double)v, mom[q]);
+              mom2[q] = fma((double)v, (double)xs[r].v[q], mom2[q]);
+            } else {
+              mom[q] = fma(rq, (double)v, mom[q]);
+            }
+          }
         }
         if (NT) stv_nt<VT, PPL>(out + off, o);
         else stv<VT, PPL>(out + off, o);
@@ -213,8 +227,9 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
       }
     }
   }
-  if (mom_on) {
-    if (cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+  if (mom_on && cur_pt >= 0) {
+    flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+    if (DBL) flush_tile<PPL>(mom2, red, wave, lane, prow2, cur_pt);
   }
 }
 
@@ -226,7 +241,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
 // through the scalar cache instead serializes: sixteen waves per CU on
 // different block rows overflow it.)
 // ---------------------------------------------------------------------------
-template <typename VT, typename MT, int PPL, int U, bool NT, bool ACC>
+template <typename VT, typename MT, int PPL, int U, bool NT, int MODE>
 __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   constexpr int BD = 9, BB = 81;
   constexpr int CH = U * BB;                       // H_hat values per chunk
@@ -242,10 +257,12 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   const bool has_prev = a.c2 != 0.0;
   const bool add_r = a.beta != nullptr;
   const bool mom_on = a.part != nullptr;
-  const bool need_r = add_r || mom_on;
+  // MODE 1: density accumulator terms; MODE 2: doubling moments <y,y>, <y,y_k>
+  // instead of r.y (the MODE 0 variants carry no code for either)
+  constexpr bool DBL = MODE == 2;
+  const bool need_r = add_r || (mom_on && !DBL);
   const double beta = add_r ? sld(a.beta) : 0.0;
-  // accumulator terms of this pass (the ACC = false variants carry no code for it)
-  const int m = ACC ? a.acc_terms : 0;
+  const int m = MODE == 1 ? a.acc_terms : 0;
   VT al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
@@ -255,17 +272,22 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   MT *hw = hs[wave];
   double *prow = mom_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
 
-  double mom[PPL];
+  double mom[PPL], mom2[PPL];
 #pragma unroll
-  for (int q = 0; q < PPL; ++q) mom[q] = 0.0;
+  for (int q = 0; q < PPL; ++q) mom[q] = mom2[q] = 0.0;
   int cur_pt = -1;
+  double *prow2 = DBL && mom_on ? a.part2 + (int64_t)blockIdx.x * sp : nullptr;
   if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
+  if (DBL && mom_on) zero_partials<PPL>(prow2, a.n_pt, wave, lane);
 
   for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
     const int pt = sc.pt();
     const int64_t rg = sc.rg();
     if (pt != cur_pt) {
-      if (mom_on && cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+      if (mom_on && cur_pt >= 0) {
+        flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+        if (DBL) flush_tile<PPL>(mom2, red, wave, lane, prow2, cur_pt);
+      }
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
@@ -332,7 +354,7 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
         const int64_t off = row * sp + c0;
         VecN<VT, PPL> pv, xs;
         if (has_prev) pv = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
-        if (m >= 2) xs = ldv<VT, PPL>(x + off);
+        if (m >= 2 || DBL) xs = ldv<VT, PPL>(x + off);
         double r[PPL];
         if (need_r) {
           if (a.sgn) {
@@ -352,7 +374,14 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
           if (has_prev) v = fma(c2, pv.v[q], v);
           if (add_r) v = (VT)((double)v + beta * r[q]);
           o.v[q] = v;
-          if (mom_on) mom[q] = fma(r[q], (double)v, mom[q]);
+          if (mom_on) {
+            if (DBL) {
+              mom[q] = fma((double)v, (double)v, mom[q]);
+              mom2[q] = fma((double)v, (double)xs.v[q], mom2[q]);
+            } else {
+              mom[q] = fma(r[q], (double)v, mom[q]);
+            }
+          }
         }
         if (NT) stv_nt<VT, PPL>(out + off, o);
         else stv<VT, PPL>(out + off, o);
@@ -365,8 +394,9 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
       }
     }
   }
-  if (mom_on) {
-    if (cur_pt >= 0) flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+  if (mom_on && cur_pt >= 0) {
+    flush_tile<PPL>(mom, red, wave, lane, prow, cur_pt);
+    if (DBL) flush_tile<PPL>(mom2, red, wave, lane, prow2, cur_pt);
   }
 }
 
@@ -428,31 +458,41 @@ __global__ __launch_bounds__(kWG) void k_init(InitArgs a) {
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename VT, typename MT, int PPL, bool ACC>
+template <typename VT, typename MT, int PPL, int MODE>
 const void *step_fn(int bd, int rpi) {
   // 1x1: rpi = rows per wave iteration; 9x9: rpi = blocks per gather chunk
   if (bd == 1)
-    return rpi == 2 ? (const void *)k_step1<VT, MT, PPL, 8, 2, true, ACC>
-                    : (const void *)k_step1<VT, MT, PPL, 8, 1, true, ACC>;
-  return rpi == 2 ? (const void *)k_step9<VT, MT, PPL, 2, true, ACC>
-                  : (const void *)k_step9<VT, MT, PPL, 1, true, ACC>;
+    return rpi == 2 ? (const void *)k_step1<VT, MT, PPL, 8, 2, true, MODE>
+                    : (const void *)k_step1<VT, MT, PPL, 8, 1, true, MODE>;
+  return rpi == 2 ? (const void *)k_step9<VT, MT, PPL, 2, true, MODE>
+                  : (const void *)k_step9<VT, MT, PPL, 1, true, MODE>;
 }
 
-template <typename VT, typename MT, bool ACC>
+template <typename VT, typename MT, int MODE>
 const void *step_fn_t(int bd, int ppl, int rpi) {
   switch (ppl) {
-    case 1: return step_fn<VT, MT, 1, ACC>(bd, rpi);
-    case 2: return step_fn<VT, MT, 2, ACC>(bd, rpi);
-    case 4: return step_fn<VT, MT, 4, ACC>(bd, rpi);
+    case 1: return step_fn<VT, MT, 1, MODE>(bd, rpi);
+    case 2: return step_fn<VT, MT, 2, MODE>(bd, rpi);
+    case 4: return step_fn<VT, MT, 4, MODE>(bd, rpi);
     default: return nullptr;
   }
 }
 
-const void *select_step(int bd, int precision, int ppl, int rpi, bool acc) {
+template <typename VT, typename MT>
+const void *step_fn_m(int bd, int ppl, int rpi, int mode) {
+  switch (mode) {
+    case 0: return step_fn_t<VT, MT, 0>(bd, ppl, rpi);
+    case 1: return step_fn_t<VT, MT, 1>(bd, ppl, rpi);
+    case 2: return step_fn_t<VT, MT, 2>(bd, ppl, rpi);
+    default: return nullptr;
+  }
+}
+
+// mode: 0 plain, 1 density accumulator, 2 doubling moments
+const void *select_step(int bd, int precision, int ppl, int rpi, int mode) {
   if ((bd != 1 && bd != 9) || rpi < 1 || rpi > 2) return nullptr;
-  if (precision == 0)
-    return acc ? step_fn_t<double, double, true>(bd, ppl, rpi) : step_fn_t<double, double, false>(bd, ppl, rpi);
-  return acc ? step_fn_t<float, float, true>(bd, ppl, rpi) : step_fn_t<float, float, false>(bd, ppl, rpi);
+  return precision == 0 ? step_fn_m<double, double>(bd, ppl, rpi, mode)
+                        : step_fn_m<float, float>(bd, ppl, rpi, mode);
 }
 
 const void *select_init(int precision, int ppl) {
@@ -475,7 +515,7 @@ const void *select_init(int precision, int ppl) {
 }  // namespace
 
 int step_blocks_per_cu(int bd, int precision, int ppl, int rpi) {
-  const void *f = select_step(bd, precision, ppl, rpi, false);
+  const void *f = select_step(bd, precision, ppl, rpi, 0);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -483,7 +523,7 @@ int step_blocks_per_cu(int bd, int precision, int ppl, int rpi) {
 }
 
 hipError_t launch_step(int bd, int precision, int ppl, const StepArgs &a, hipStream_t s) {
-  const void *f = select_step(bd, precision, ppl, a.rpi, a.acc != nullptr && a.acc_terms > 0);
+  const void *f = select_step(bd, precision, ppl, a.rpi, step_mode(a));
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);

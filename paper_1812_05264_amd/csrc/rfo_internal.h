@@ -38,7 +38,9 @@ struct StepArgs {
   void *acc;               // density accumulator or nullptr
   const double *alpha;     // device array: alpha^f of the acc_terms newest terms, oldest first
   int acc_terms;           // 0..3; 3 needs prev (c2 != 0)
-  double *part;            // [n_rg][sp] moment partials (ring slot) or nullptr
+  double *part;            // [grid][sp] moment partials (ring slot) or nullptr
+  double *part2;           // doubling moments: part gets <y_{k+1}, y_{k+1}>, part2
+                           // <y_{k+1}, y_k> (instead of r . y_{k+1}); nullptr = off
   int64_t nb;              // block rows
   int sp;
   int rows_per_wg;
@@ -46,6 +48,13 @@ struct StepArgs {
   int rpi;                 // rows per wave iteration (1x1 blocks: 1 or 2)
   int grid;                // workgroups (multiple of 8); part has [grid][sp]
 };
+
+// Kernel variant of a step: 1 = density accumulator terms, 2 = doubling
+// moments, 0 = neither (the two are not combined).
+inline int step_mode(const StepArgs &a) {
+  if (a.acc != nullptr && a.acc_terms > 0) return 1;
+  return a.part2 != nullptr ? 2 : 0;
+}
 
 // precision: 0 = fp64 (double vectors, double H), 1 = fp32 (float vectors, float H)
 hipError_t launch_step(int bd, int precision, int ppl, const StepArgs &a, hipStream_t s);
@@ -98,10 +107,13 @@ hipError_t launch_coefficients(double e_min, double e_max, double T, double mu,
                                double *costab, double *coef, hipStream_t s);
 // Fixed-order reduction of moment partials: moments[k][c] for k in
 // [k0, k0 + count), ring slot of index k is k % ring.  Flags a moment that
-// exceeds (1 + tol) * moments[0][c].
+// exceeds (1 + tol) * moments[0][c].  dbl: the partials are the doubling inner
+// products and moment k >= 2 is 2 * sum - moments[k mod 2] (moments 0 and 1
+// must be final before the launch).
 hipError_t launch_moment_reduce(const double *part, int ring, int64_t k0,
                                 int count, int n_rg, int sp, double *moments,
-                                int check, double tol, int *flags, hipStream_t s);
+                                int check, double tol, int *flags, int dbl,
+                                hipStream_t s);
 // N, E, F from moments and coefficients.
 hipError_t launch_traces(const double *moments, const double *w,
                          const double *coef, int64_t p, int sp, double *out3,

@@ -46,6 +46,11 @@ def test_fermi_moments_match_oracle(name):
     for key in ("N", "E", "F"):
         assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
     assert rel(g["density"], o["density"]) < TOL
+    # without density the moments come from the doubling identities
+    d = eng.fermi_moments(T, mu, p, moments=True)
+    assert rel(d["moments"], o["moments"]) < TOL
+    for key in ("N", "E", "F"):
+        assert abs(d[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
 
 
 @pytest.mark.parametrize("bd", [1, 9])
@@ -63,6 +68,28 @@ def test_density_short_series(bd):
         o = est.estimate(H, R, 0.2, 0.1, p, density=True)
         assert rel(g["moments"], o["moments"]) < TOL, p
         assert rel(g["density"], o["density"]) < TOL, p
+
+
+@pytest.mark.parametrize("bd", [1, 9])
+def test_doubling_short_series_and_direct_path(bd):
+    """Doubling runs floor(p/2) steps: series of 1..9 terms hit both parities of
+    p and the first steps that produce mu_1 and mu_2; the direct path (doubling
+    off) gives the same moments up to rounding."""
+    banner(f"doubling moments bd={bd}")
+    eng = engine_or_skip()
+    H = simple_cubic(6, disorder=0.5, config_id=24) if bd == 1 else cu_cluster(19, config_id=24).bsr()
+    R = rademacher(H.n, 72, config_id=501)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    for p in list(range(1, 10)) + [64, 65]:
+        g = eng.fermi_moments(0.2, 0.1, p, moments=True)
+        o = est.estimate(H, R, 0.2, 0.1, p)
+        assert rel(g["moments"], o["moments"]) < TOL, p
+        eng.set_moment_doubling(False)
+        d = eng.fermi_moments(0.2, 0.1, p, moments=True)
+        eng.set_moment_doubling(True)
+        assert rel(g["moments"], d["moments"]) < 1e-13, p
+        assert abs(g["F"] - d["F"]) <= 1e-12 * abs(d["F"]), p
 
 
 def test_config_sc8_against_closed_form():

@@ -36,6 +36,11 @@ def test_fp32_against_oracle(name, build, s, T, mu, p):
     eN = abs(g["N"] - o["N"]) / abs(o["N"])
     print(f"fp32 {name}: moments {em:.2e} density {ed:.2e} N {eN:.2e}")
     assert em < 1e-5 and ed < 1e-5 and eN < 1e-6
+    d = eng.fermi_moments(T, mu, p, moments=True)        # doubling moments
+    ed2 = rel(d["moments"], o["moments"])
+    eN2 = abs(d["N"] - o["N"]) / abs(o["N"])
+    print(f"fp32 {name} doubling: moments {ed2:.2e} N {eN2:.2e}")
+    assert ed2 < 1e-5 and eN2 < 1e-6
 
 
 @pytest.mark.parametrize("name,atoms,s,p", [("cu55_s64", 55, 64, 120), ("cu201_s100", 201, 100, 120),
@@ -56,6 +61,11 @@ def test_bf16_mfma_against_oracle(name, atoms, s, p):
     print(f"bf16 {name}: moments {em:.2e} density {ed:.2e} N {eN:.2e} E {eE:.2e}")
     assert np.all(g["moments"][:, 0] == o["moments"][:, 0])   # mu_0 = ||r||^2 is exact
     assert em < 3e-2 and ed < 3e-2 and eN < 1e-2 and eE < 1e-2
+    d = eng.fermi_moments(T, mu, p, moments=True)        # doubling moments
+    ed2 = rel(d["moments"], o["moments"])
+    eN2 = abs(d["N"] - o["N"]) / abs(o["N"])
+    print(f"bf16 {name} doubling: moments {ed2:.2e} N {eN2:.2e}")
+    assert ed2 < 3e-2 and eN2 < 1e-2
 
 
 def test_bf16_density_short_series():

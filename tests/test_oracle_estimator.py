@@ -147,3 +147,20 @@ def test_weights_and_probe_normalisation(sc6):
     m = est.moments(est.mapped_hamiltonian(H), R, 32)
     assert np.all(m[:, 0] == H.n)
     assert np.all(np.abs(m) <= H.n * (1 + 1e-12))
+
+
+def test_doubling_identities_hold_for_oracle_vectors():
+    """T_2j = 2 T_j^2 - T_0 and T_2j-1 = 2 T_j T_j-1 - T_1 (product formula of
+    cos): moments rebuilt from inner products of y_j = T_j(H_hat) r equal the
+    direct moments r . y_k."""
+    H = simple_cubic(4, disorder=0.7, config_id=5)
+    R = rademacher(H.n, 5, config_id=6)
+    Hh = est.mapped_hamiltonian(H)
+    p = 21
+    ys = list(est.chebyshev_vectors(Hh, R, p))
+    mu = est.moments(Hh, R, p)              # [s][p]
+    for j in range(1, (p - 1) // 2 + 1):
+        two_j = 2 * np.einsum("ic,ic->c", ys[j], ys[j]) - mu[:, 0]
+        assert np.allclose(two_j, mu[:, 2 * j], rtol=0, atol=1e-11 * H.n)
+        two_jm1 = 2 * np.einsum("ic,ic->c", ys[j], ys[j - 1]) - mu[:, 1]
+        assert np.allclose(two_jm1, mu[:, 2 * j - 1], rtol=0, atol=1e-11 * H.n)
