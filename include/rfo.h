@@ -129,8 +129,11 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
 /* Free energy F~ and its gradient dF~/dH on H's block pattern (paper:
  * Analytical free-energy derivatives, polynomial form; the interval is held
  * fixed, so dF/dH = 2/(e_max - e_min) dF/dH_hat).  The forward pass keeps
- * checkpoints every ceil(sqrt(p - 1)) steps and the backward pass replays one
- * segment at a time, so memory grows with sqrt(p) vectors, not p.
+ * checkpoints every ceil(sqrt(steps)) steps and the backward pass replays one
+ * segment at a time, so memory grows with sqrt(p) vectors, not p.  With moment
+ * doubling on (rfo_set_moment_doubling, the default) F~ is taken through the
+ * doubled moments of floor(p/2) steps and the backward recurrence carries
+ * their vector sources; the result is the same gradient up to rounding.
  *   NEF_out   [3]  N, E, F of the forward pass (nullable)
  *   dFdH_out  [nnzb][bd][bd]  raw gradient G (nullable)
  * The gradient also stays on the device for rfo_hf_forces. */

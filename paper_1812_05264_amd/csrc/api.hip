@@ -290,7 +290,7 @@ struct Checkpoints {
 
 int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_acc,
                 const Checkpoints *ck, size_t *n_events, bool dbl = false) {
-  if (dbl && (use_acc || ck)) return fail(ctx, RFO_E_INVALID, "doubling moments need all y_k");
+  if (dbl && use_acc) return fail(ctx, RFO_E_INVALID, "the density needs every y_k");
   const int kp = kernel_precision(ctx);
   const double tol = ctx->prec == RFO_FP64 ? 1e-6 : (ctx->prec == RFO_FP32 ? 1e-3 : 1e-2);
   const size_t slot = (size_t)pl.grid * ctx->sp;
@@ -715,6 +715,163 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
   return RFO_OK;
 }
 
+// Free energy and gradient with the doubling moments: the forward pass runs
+// K = floor(p/2) steps and F~ = const + sum_j a_j <y_j, y_j> + b_j <y_j, y_{j-1}>
+// (a_j = 2 beta_2j, b_j = 2 beta_2j-1, b_1 = beta_1 - sum_{j>=2} beta_2j-1 for
+// the terms below p).  Reverse recurrence as in the direct form, with the
+// vector source g_j = dF~/dy_j = 2 a_j y_j + b_j y_{j-1} + b_{j+1} y_{j+1}:
+//   z_K = g_K, z_{K-1} = g_{K-1} + 2 H_hat z_K, z_j = g_j + 2 H_hat z_{j+1} - z_{j+2},
+//   dF~/dH_hat = z_1 y_0^T + 2 sum_{j=1}^{K-1} z_{j+1} y_j^T,
+// symmetrized (the doubled form is a function of H_hat^T as well as H_hat; the
+// gradient of F~ on symmetric matrices is the symmetric part).
+int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_out,
+                         double *dFdH_out) {
+  const int kp = kernel_precision(ctx);
+  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
+  const int64_t K = p / 2;
+  int64_t m = 2;
+  while (m * m < K) ++m;
+  const int64_t Q = (K + m - 1) / m;
+  // vector slots: ys [m + 2] | zs [m + 2] | checkpoints [2 (Q - 1)]
+  const int64_t n_ys = m + 2, n_zs = m + 2, n_ck = Q > 1 ? 2 * (Q - 1) : 0;
+  TRY(ensure(ctx, ctx->vec, (size_t)(n_ys + n_zs + n_ck) * pl.vec_elems * pl.vt_bytes));
+  DevBuf ckview;
+  ckview.p = vec_at(ctx, pl, ctx->vec, n_ys + n_zs);
+  ckview.bytes = (size_t)n_ck * pl.vec_elems * pl.vt_bytes;
+  Checkpoints ck;
+  ck.m = m;
+  ck.Q = Q;
+  ck.store = &ckview;
+  size_t n_events = 0;
+  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, &n_events, true));
+  double *obs = P<double>(ctx->small);
+  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
+                            ctx->sp, obs, ctx->stream));
+  // source weights from beta^g (host copy of the device coefficients)
+  std::vector<double> beta((size_t)p);
+  HIPCHK(hipMemcpyAsync(beta.data(), P<double>(ctx->coef) + 2 * p, p * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<double> a(K + 2, 0.0), b(K + 2, 0.0);
+  for (int64_t j = 1; j <= K; ++j) {
+    if (2 * j <= p - 1) a[j] = 2.0 * beta[2 * j];
+    if (j >= 2 && 2 * j - 1 <= p - 1) b[j] = 2.0 * beta[2 * j - 1];
+  }
+  b[1] = beta[1];
+  for (int64_t j = 2; j <= K; ++j)
+    if (2 * j - 1 <= p - 1) b[1] -= beta[2 * j - 1];
+
+  const size_t vb = pl.vec_elems * pl.vt_bytes;
+  auto ys = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, t); };
+  auto zs = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, n_ys + t); };
+  auto cka = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_ys + n_zs + 2 * (q - 1)); };
+  auto ckb = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_ys + n_zs + 2 * (q - 1) + 1); };
+  rfo::StepArgs sa;
+  fill_step(ctx, pl, sa);
+  rfo::InitArgs ia;
+  fill_init(ctx, pl, ia);
+  for (int64_t q = Q - 1; q >= 0; --q) {
+    const int64_t j0 = q * m, j1 = std::min(j0 + m, K), len = j1 - j0;
+    // replay y_j, j in [j0, min(j1 + 2, K + 1)), into ys[0 ..): the sources of
+    // z_{j1} and z_{j1-1} need y_{j1} and y_{j1+1}
+    const int64_t rlen = std::min(j1 + 2, K + 1) - j0;
+    if (q == 0) {
+      ia.out = ys(0);
+      ia.scale = nullptr;
+      ia.acc = nullptr;
+      ia.part = nullptr;
+      HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(ys(0), ckb(q), vb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    sa.beta = nullptr;
+    sa.acc = nullptr;
+    sa.part = nullptr;
+    sa.part2 = nullptr;
+    for (int64_t t = 1; t < rlen; ++t) {
+      sa.x = ys(t - 1);
+      if (t == 1) {
+        sa.prev = (j0 == 0) ? nullptr : cka(q);
+        sa.c1 = (j0 == 0) ? 1.0 : 2.0;
+        sa.c2 = (j0 == 0) ? 0.0 : -1.0;
+      } else {
+        sa.prev = ys(t - 2);
+        sa.c1 = 2.0;
+        sa.c2 = -1.0;
+      }
+      sa.out = ys(t);
+      sa.nsrc = 0;
+      HIPCHK(launch_any_step(ctx, pl, sa));
+    }
+    // reverse: zs[t] = z_i, i = j0 + 1 + t; y_i is ys[t + 1]
+    for (int64_t t = len - 1; t >= 0; --t) {
+      const int64_t i = j0 + 1 + t;
+      sa.src[0] = ys(t + 1);
+      sa.srcw[0] = 2.0 * a[i];
+      sa.src[1] = ys(t);
+      sa.srcw[1] = b[i];
+      sa.nsrc = 2;
+      if (i + 1 <= K) {
+        sa.src[2] = ys(t + 2);
+        sa.srcw[2] = b[i + 1];
+        sa.nsrc = 3;
+      }
+      if (i == K) {
+        sa.x = ys(t + 1);  // any valid vector: c1 = 0
+        sa.prev = nullptr;
+        sa.c1 = 0.0;
+        sa.c2 = 0.0;
+      } else {
+        sa.x = zs(t + 1);
+        sa.prev = (i == K - 1) ? nullptr : zs(t + 2);
+        sa.c1 = 2.0;
+        sa.c2 = (i == K - 1) ? 0.0 : -1.0;
+      }
+      sa.out = zs(t);
+      HIPCHK(launch_any_step(ctx, pl, sa));
+    }
+    sa.nsrc = 0;
+    // G += 1/2 sum_{j in segment} c_j (z_{j+1} y_j^T + y_j z_{j+1}^T) on the blocks on
+    // and above the diagonal, c_0 = 1, c_j = 2; times 2/(e_max - e_min)
+    rfo::SddmmArgs sd;
+    memset(&sd, 0, sizeof(sd));
+    sd.brow = P<int64_t>(ctx->brow);
+    sd.col = P<int32_t>(ctx->col);
+    sd.nnzb = ctx->nnzb;
+    sd.bd = ctx->bd;
+    sd.sp = ctx->sp;
+    sd.xbase = zs(0);
+    sd.xstride = (int64_t)pl.vec_elems;
+    sd.ybase = ys(0);
+    sd.ystride = (int64_t)pl.vec_elems;
+    sd.w = P<double>(ctx->w);
+    sd.count = (int)len;
+    sd.j0 = j0;
+    sd.scale = 1.0 / (ctx->e_max - ctx->e_min);
+    sd.first = 1.0;
+    sd.rest = 2.0;
+    sd.G = P<double>(ctx->G);
+    sd.accumulate = (q == Q - 1) ? 0 : 1;
+    sd.nzlist = P<int64_t>(ctx->nz_up);
+    sd.nlist = ctx->n_up;
+    sd.ppl = sddmm_ppl(ctx);
+    sd.sym = 1;
+    HIPCHK(rfo::launch_sddmm(kp, sd, ctx->stream));
+    if (q > 0) {
+      // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}
+      HIPCHK(hipMemcpyAsync(zs(m), zs(0), vb, hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(zs(m + 1), zs(1), vb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+  }
+  HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
+                            P<double>(ctx->G), ctx->stream));
+  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
+  TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
+  TRY(check_flags_and_finish(ctx, n_events));
+  ctx->has_grad = true;
+  return RFO_OK;
+}
+
 int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double *NEF_out,
                         double *dFdH_out) {
   if (!ctx) return RFO_E_INVALID;
@@ -722,6 +879,11 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   Plan pl;
   TRY(prepare_call(ctx, T, mu, n_terms, pl));
   const int64_t p = n_terms;
+  if (ctx->doubling && p >= 2) {
+    TRY(ensure(ctx, ctx->G, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
+    ctx->has_grad = false;
+    return energy_grad_doubling(ctx, pl, p, NEF_out, dFdH_out);
+  }
   const int kp = kernel_precision(ctx);
   const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
   TRY(ensure(ctx, ctx->G, gbytes));

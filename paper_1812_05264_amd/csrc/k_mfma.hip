@@ -56,6 +56,16 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   const bool need_r = add_r || (mom_on && !DBL);
   const double beta = add_r ? sld(a.beta) : 0.0;
   const int m = MODE == 1 ? a.acc_terms : 0;
+  // MODE 3: vector sources added to the output (reverse recurrence with doubling)
+  constexpr bool SRC = MODE == 3;
+  const int nsrc = SRC ? a.nsrc : 0;
+  const float *srcp[3];
+  float srw[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    srcp[t] = t < nsrc ? static_cast<const float *>(a.src[t]) : nullptr;
+    srw[t] = t < nsrc ? (float)a.srcw[t] : 0.f;
+  }
   float al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (float)sld(a.alpha + i) : 0.f;
@@ -177,6 +187,12 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
         const int64_t off = row * sp + cp;
         const VecN<float, NT> pv = pv4[i];
         const uint64_t sw = sw4[i];
+        VecN<float, NT> sv[3];
+        if (SRC) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            if (t < nsrc) sv[t] = ldv_nt<float, NT>(srcp[t] + off);
+        }
         VecN<double, NT> rv;
         if (need_r && !a.sgn) rv = ldv<double, NT>(a.rden + off);
         VecN<float, NT> o;
@@ -187,6 +203,11 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
           float v = c1 * d[t][i];
           if (has_prev) v = fmaf(c2, pv.v[t], v);
           if (add_r) v = (float)((double)v + beta * rq);
+          if (SRC) {
+#pragma unroll
+            for (int tt = 0; tt < 3; ++tt)
+              if (tt < nsrc) v = fmaf(srw[tt], sv[tt].v[t], v);
+          }
           o.v[t] = v;
           if (mom_on) {
             if (DBL) {
@@ -239,9 +260,10 @@ namespace {
 const void *select_bf16(int nt_tiles, int u, int mode) {
 #define RFO_BF16_CASE(T, UU)                                                        \
   if (nt_tiles == T && u == UU)                                                     \
-    return mode == 1 ? (const void *)k_step9_bf16<T, UU, true, 1>                   \
-                     : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2>       \
-                                 : (const void *)k_step9_bf16<T, UU, true, 0>;
+    return mode == 1   ? (const void *)k_step9_bf16<T, UU, true, 1>                 \
+           : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2>                 \
+           : mode == 3 ? (const void *)k_step9_bf16<T, UU, true, 3>                 \
+                       : (const void *)k_step9_bf16<T, UU, true, 0>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
   RFO_BF16_CASE(8, 1)

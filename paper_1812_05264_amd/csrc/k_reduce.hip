@@ -16,7 +16,7 @@
 
 namespace rfo {
 
-template <int BD, typename VT, int PPL>
+template <int BD, typename VT, int PPL, bool SYM>
 __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -39,8 +39,16 @@ __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
     const VT *Y = a.ybase ? static_cast<const VT *>(a.ybase) + (int64_t)t * a.ystride : nullptr;
     for (int c = lane * PPL; c < sp; c += 64 * PPL) {
       VecN<VT, PPL> xv[BD], yv[BD];
+      VecN<VT, PPL> xj[SYM ? BD : 1], yi[SYM ? BD : 1];
 #pragma unroll
       for (int i = 0; i < BD; ++i) xv[i] = ldv<VT, PPL>(X + (I * BD + i) * sp + c);
+      if constexpr (SYM) {
+#pragma unroll
+        for (int i = 0; i < BD; ++i) {
+          xj[i] = ldv<VT, PPL>(X + (J * BD + i) * sp + c);
+          yi[i] = ldv<VT, PPL>(Y + (I * BD + i) * sp + c);
+        }
+      }
       if (Y) {
 #pragma unroll
         for (int j = 0; j < BD; ++j) yv[j] = ldv<VT, PPL>(Y + (J * BD + j) * sp + c);
@@ -61,6 +69,16 @@ __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
         for (int i = 0; i < BD; ++i)
 #pragma unroll
           for (int j = 0; j < BD; ++j) s[i][j] = fma(xa[i], (double)yv[j].v[q], s[i][j]);
+        if constexpr (SYM) {
+          // + Y_I X_J^T: the symmetric part of the raw outer products
+          double ya[BD];
+#pragma unroll
+          for (int i = 0; i < BD; ++i) ya[i] = wc * (double)yi[i].v[q];
+#pragma unroll
+          for (int i = 0; i < BD; ++i)
+#pragma unroll
+            for (int j = 0; j < BD; ++j) s[i][j] = fma(ya[i], (double)xj[j].v[q], s[i][j]);
+        }
       }
     }
   }
@@ -77,14 +95,20 @@ __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
 
 template <int BD, typename VT>
 static void launch_sddmm_t(const SddmmArgs &a, dim3 grid, hipStream_t s) {
-  if (a.ppl == 2) hipLaunchKernelGGL((k_sddmm<BD, VT, 2>), grid, dim3(kWG), 0, s, a);
-  else hipLaunchKernelGGL((k_sddmm<BD, VT, 1>), grid, dim3(kWG), 0, s, a);
+  if (a.sym) {
+    if (a.ppl == 2) hipLaunchKernelGGL((k_sddmm<BD, VT, 2, true>), grid, dim3(kWG), 0, s, a);
+    else hipLaunchKernelGGL((k_sddmm<BD, VT, 1, true>), grid, dim3(kWG), 0, s, a);
+  } else {
+    if (a.ppl == 2) hipLaunchKernelGGL((k_sddmm<BD, VT, 2, false>), grid, dim3(kWG), 0, s, a);
+    else hipLaunchKernelGGL((k_sddmm<BD, VT, 1, false>), grid, dim3(kWG), 0, s, a);
+  }
 }
 
 hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s) {
   const int64_t total = a.nzlist ? a.nlist : a.nnzb;
   if (total == 0) return hipSuccess;
   if (a.ppl == 2 && (a.sp % 128) != 0) return hipErrorInvalidValue;
+  if (a.sym && !a.ybase) return hipErrorInvalidValue;
   const dim3 grid((unsigned)((total + kWaves - 1) / kWaves));
   if (a.bd == 1) {
     if (precision == 0) launch_sddmm_t<1, double>(a, grid, s);

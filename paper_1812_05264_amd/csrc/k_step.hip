@@ -91,6 +91,16 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const bool need_r = add_r || (mom_on && !DBL);
   const double beta = add_r ? sld(a.beta) : 0.0;
   const int m = MODE == 1 ? a.acc_terms : 0;
+  // MODE 3: vector sources added to the output (reverse recurrence with doubling)
+  constexpr bool SRC = MODE == 3;
+  const int nsrc = SRC ? a.nsrc : 0;
+  const VT *srcp[3];
+  VT srw[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    srcp[t] = t < nsrc ? static_cast<const VT *>(a.src[t]) : nullptr;
+    srw[t] = t < nsrc ? (VT)a.srcw[t] : (VT)0;
+  }
   VT al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
@@ -127,13 +137,18 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
         beg[r] = sld(a.row_ptr + Ir[r]);
         end[r] = sld(a.row_ptr + Ir[r] + 1);
       }
-      VecN<VT, PPL> pv[RPI], xs[RPI];
+      VecN<VT, PPL> pv[RPI], xs[RPI], sv[3][RPI];
       uint64_t sw[RPI];
       VecN<double, PPL> rv[RPI];
 #pragma unroll
       for (int r = 0; r < RPI; ++r) {
         const int64_t off = Ir[r] * sp + c0;
         if (has_prev) pv[r] = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        if (SRC) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            if (t < nsrc) sv[t][r] = ldv_nt<VT, PPL>(srcp[t] + off);
+        }
         if (need_r) {
           if (a.sgn) sw[r] = a.sgn[Ir[r] * nw + (c0 >> 6)];
           else rv[r] = ldv<double, PPL>(a.rden + off);
@@ -206,6 +221,11 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
           VT v = c1 * s[r][q];
           if (has_prev) v = fma(c2, pv[r].v[q], v);
           if (add_r) v = (VT)((double)v + beta * rq);
+          if (SRC) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+              if (t < nsrc) v = fma(srw[t], sv[t][r].v[q], v);
+          }
           o.v[q] = v;
           if (mom_on) {
             if (DBL) {
@@ -263,6 +283,16 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   const bool need_r = add_r || (mom_on && !DBL);
   const double beta = add_r ? sld(a.beta) : 0.0;
   const int m = MODE == 1 ? a.acc_terms : 0;
+  // MODE 3: vector sources added to the output (reverse recurrence with doubling)
+  constexpr bool SRC = MODE == 3;
+  const int nsrc = SRC ? a.nsrc : 0;
+  const VT *srcp[3];
+  VT srw[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    srcp[t] = t < nsrc ? static_cast<const VT *>(a.src[t]) : nullptr;
+    srw[t] = t < nsrc ? (VT)a.srcw[t] : (VT)0;
+  }
   VT al[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) al[i] = i < m ? (VT)sld(a.alpha + i) : (VT)0;
@@ -354,6 +384,12 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
         const int64_t off = row * sp + c0;
         VecN<VT, PPL> pv, xs;
         if (has_prev) pv = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        VecN<VT, PPL> sv[3];
+        if (SRC) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            if (t < nsrc) sv[t] = ldv_nt<VT, PPL>(srcp[t] + off);
+        }
         if (m >= 2 || DBL) xs = ldv<VT, PPL>(x + off);
         double r[PPL];
         if (need_r) {
@@ -373,6 +409,11 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
           VT v = c1 * s[i][q];
           if (has_prev) v = fma(c2, pv.v[q], v);
           if (add_r) v = (VT)((double)v + beta * r[q]);
+          if (SRC) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+              if (t < nsrc) v = fma(srw[t], sv[t].v[q], v);
+          }
           o.v[q] = v;
           if (mom_on) {
             if (DBL) {
@@ -484,11 +525,12 @@ const void *step_fn_m(int bd, int ppl, int rpi, int mode) {
     case 0: return step_fn_t<VT, MT, 0>(bd, ppl, rpi);
     case 1: return step_fn_t<VT, MT, 1>(bd, ppl, rpi);
     case 2: return step_fn_t<VT, MT, 2>(bd, ppl, rpi);
+    case 3: return step_fn_t<VT, MT, 3>(bd, ppl, rpi);
     default: return nullptr;
   }
 }
 
-// mode: 0 plain, 1 density accumulator, 2 doubling moments
+// mode: 0 plain, 1 density accumulator, 2 doubling moments, 3 vector sources
 const void *select_step(int bd, int precision, int ppl, int rpi, int mode) {
   if ((bd != 1 && bd != 9) || rpi < 1 || rpi > 2) return nullptr;
   return precision == 0 ? step_fn_m<double, double>(bd, ppl, rpi, mode)

@@ -41,6 +41,10 @@ struct StepArgs {
   double *part;            // [grid][sp] moment partials (ring slot) or nullptr
   double *part2;           // doubling moments: part gets <y_{k+1}, y_{k+1}>, part2
                            // <y_{k+1}, y_k> (instead of r . y_{k+1}); nullptr = off
+  // vector sources: out += sum_{t < nsrc} srcw[t] * src[t] (same layout as out)
+  const void *src[3];
+  double srcw[3];
+  int nsrc;
   int64_t nb;              // block rows
   int sp;
   int rows_per_wg;
@@ -50,10 +54,11 @@ struct StepArgs {
 };
 
 // Kernel variant of a step: 1 = density accumulator terms, 2 = doubling
-// moments, 0 = neither (the two are not combined).
+// moments, 3 = vector sources, 0 = none (they are not combined).
 inline int step_mode(const StepArgs &a) {
   if (a.acc != nullptr && a.acc_terms > 0) return 1;
-  return a.part2 != nullptr ? 2 : 0;
+  if (a.part2 != nullptr) return 2;
+  return a.nsrc > 0 ? 3 : 0;
 }
 
 // precision: 0 = fp64 (double vectors, double H), 1 = fp32 (float vectors, float H)
@@ -143,6 +148,7 @@ struct SddmmArgs {
   const int64_t *nzlist;   // blocks to compute (nullptr = all nnzb)
   int64_t nlist;
   int ppl;                 // probes per lane per load (1 or 2)
+  int sym;                 // G[nz] (+)= sum_t coef_t sum_c w_c (X_I Y_J^T + Y_I X_J^T)
 };
 hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s);
 // G[nz] = G[tpos[nz]]^T for the listed blocks (completes a symmetric gradient).

@@ -133,14 +133,22 @@ GRAD_CASES = {
     "cu55_p2": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 2),
     "cu55_p3": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 3),
     "graph300_grad": (lambda: random_graph(300, config_id=32), 9, 0.5, 0.2, 41),
+    "cu55_p4": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 4),
+    "cu55_p5": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 5),
+    # several checkpoint segments with the doubling (K = 150, segments of 13)
+    "sc6_p301": (lambda: simple_cubic(6, disorder=0.3, config_id=30), 5, 0.1, 0.2, 301),
 }
 
 
+@pytest.mark.parametrize("doubling", [True, False])
 @pytest.mark.parametrize("name", list(GRAD_CASES))
-def test_gradient_matches_oracle(name):
+def test_gradient_matches_oracle(name, doubling):
+    """doubling: floor(p/2) forward steps and the reverse recurrence of the
+    doubled moments; otherwise the reverse recurrence of r . y_k over p - 1."""
     build, s, T, mu, p = GRAD_CASES[name]
-    banner(f"gradient parity {name}")
+    banner(f"gradient parity {name} doubling={doubling}")
     eng = engine_or_skip()
+    eng.set_moment_doubling(doubling)
     obj = build()
     H = obj.bsr() if hasattr(obj, "bsr") else obj
     R = rademacher(H.n, s, config_id=501)
