@@ -17,8 +17,9 @@ Also reported on the same line:
   roofline      for the Chebyshev step kernel, from HIP events around its launches
   cpu_baseline  the FP64 oracle's Chebyshev steps on the host (bounded sample)
   energy_force  energy + gradient + Hellmann-Feynman forces on the 16,000-atom
-                Cu-like cluster (8000 terms, 256 probes), FP64 and FP32, with the
-                FP32 errors against FP64 per atom
+                Cu-like cluster (8000 terms, 256 probes), FP64 and FP32 with the
+                doubled moments (the library default), and FP64 with the direct
+                recurrence, with the errors against the FP64 doubled result per atom
 """
 
 import argparse
@@ -102,20 +103,25 @@ def energy_force(args):
     out = {"workload": "cu16k_grad", "atoms": cl.n_atoms, "orbitals": H.n, "nnzb": H.nnzb,
            "n_terms": n_terms, "probes": cfg.n_probes, "T_eV": cfg.T, "mu_eV": cfg.mu}
     res = {}
-    for prec in args.ef_precisions.split(","):
+    runs = [(prec, True) for prec in args.ef_precisions.split(",")]
+    if args.ef_direct:
+        runs.append(("fp64", False))
+    import torch
+    for prec, doubling in runs:
         eng = pkg.Engine(0)
         eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, prec)
         eng.set_probes(R)
-        import torch
+        eng.set_moment_doubling(doubling)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g = eng.energy_and_dEdH(cfg.T, cfg.mu, n_terms, gradient=False)
         f = eng.hf_forces(D)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        res[prec] = (dt, g, f)
-        out[f"seconds_{prec}"] = round(dt, 4)
-        print(f"[bench] energy_force {prec}: {dt:.3f} s  F={g['F']:.6f} E={g['E']:.6f}", flush=True)
+        key = prec if doubling else f"{prec}_direct"
+        res[key] = (dt, g, f)
+        out[f"seconds_{key}"] = round(dt, 4)
+        print(f"[bench] energy_force {key}: {dt:.3f} s  F={g['F']:.6f} E={g['E']:.6f}", flush=True)
         eng.close()
         del eng
     if "fp64" in res:
@@ -142,6 +148,8 @@ def main():
                     help="oracle Chebyshev steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--energy-force", type=int, default=1)
     ap.add_argument("--ef-precisions", default="fp64,fp32")
+    ap.add_argument("--ef-direct", type=int, default=1,
+                    help="also time FP64 energy_force with the direct recurrence (no doubling)")
     ap.add_argument("--ef-terms", type=int, default=0,
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
@@ -206,9 +214,11 @@ def main():
     total_bytes = b_step * (p - 1) * args.steps
     value = total_bytes / wall / 1e9
     achieved = b_step / (step_ms * 1e-3) / 1e9
-    kname = ("k_step1<double, double, 2, 8, 1, true>" if args.precision == "fp64"
-             else "k_step1<float, float, 4, 8, 1, true>")
-    traffic = measured_traffic(kname)
+    # the step kernel is launched as two variants: MODE 1 on the steps that
+    # update the density accumulator, MODE 0 on the others
+    kname = ("k_step1<double, double, 2, 8, 1, true, MODE>" if args.precision == "fp64"
+             else "k_step1<float, float, 4, 8, 1, true, MODE>")
+    traffic = measured_traffic("sc64_" + args.precision)
     print(f"[bench] sc64 {args.precision}: {wall / args.steps * 1e3:.1f} ms per call, step kernel "
           f"{step_ms * 1e3:.1f} us ({n_steps} steps), {achieved:.0f} GB/s, N={last['N']:.6f}",
           flush=True)
