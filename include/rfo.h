@@ -126,6 +126,14 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
                       double *moments_out, double *NEF_out,
                       double *density_out);
 
+/* N, E, F at another (T, mu) from the moments of the last rfo_fermi_moments or
+ * rfo_energy_and_dEdH call (the moments do not depend on T or mu; only the
+ * coefficients are recomputed, paper: Polynomial approximation).  Used for
+ * scans of mu at fixed electron count.  NEF_out [3] host or device memory.
+ * Errors: RFO_E_STATE before any call, or after rfo_set_hamiltonian /
+ * rfo_set_probes invalidated the moments. */
+int rfo_traces_at(rfo_ctx *ctx, double T, double mu, double *NEF_out);
+
 /* Free energy F~ and its gradient dF~/dH on H's block pattern (paper:
  * Analytical free-energy derivatives, polynomial form; the interval is held
  * fixed, so dF/dH = 2/(e_max - e_min) dF/dH_hat).  The forward pass keeps

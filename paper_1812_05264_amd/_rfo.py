@@ -55,10 +55,11 @@ def load():
     lib.rfo_hf_forces.argtypes = [vp, vp, vp]
     lib.rfo_set_timing.argtypes = [vp, i32]
     lib.rfo_set_moment_doubling.argtypes = [vp, i32]
+    lib.rfo_traces_at.argtypes = [vp, dbl, dbl, ctypes.POINTER(dbl)]
     lib.rfo_step_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for f in ("rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
               "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing",
-              "rfo_step_timing", "rfo_set_moment_doubling"):
+              "rfo_step_timing", "rfo_set_moment_doubling", "rfo_traces_at"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -200,6 +201,12 @@ class Engine:
         return out
 
     # -- instrumentation --------------------------------------------------------------
+    def traces_at(self, T, mu):
+        """N, E, F at (T, mu) from the moments of the last fermi_moments / energy call."""
+        out = (ctypes.c_double * 3)()
+        self._check(self._lib.rfo_traces_at(self._ctx, float(T), float(mu), out))
+        return {"N": out[0], "E": out[1], "F": out[2]}
+
     def set_moment_doubling(self, enabled=True):
         """Moment-only fermi_moments calls run floor(p/2) steps (doubling identities)."""
         self._check(self._lib.rfo_set_moment_doubling(self._ctx, 1 if enabled else 0))

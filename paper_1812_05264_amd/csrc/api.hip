@@ -51,6 +51,7 @@ struct rfo_ctx {
   bool has_grad = false;
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
+  int64_t mom_p = 0;     // moments of the last call still valid on the device (0 = none)
 
   // instrumentation
   bool timing = false;
@@ -480,6 +481,7 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
                         double e_max, int precision) {
   if (!ctx) return RFO_E_INVALID;
   ctx->err.clear();
+  ctx->mom_p = 0;
   if (block_dim != 1 && block_dim != 9)
     return fail(ctx, RFO_E_INVALID, "block_dim must be 1 or 9 (got %d)", block_dim);
   if (n_block_rows < 1 || n_block_rows > ((int64_t)1 << 30))
@@ -635,6 +637,7 @@ int rfo_get_interval(const rfo_ctx *ctx, double *e_min, double *e_max) {
 int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R, const double *weights) {
   if (!ctx) return RFO_E_INVALID;
   ctx->err.clear();
+  ctx->mom_p = 0;
   if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "set the Hamiltonian before the probes");
   if (!R) return fail(ctx, RFO_E_INVALID, "R is NULL");
   if (n_probes < 1 || n_probes > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_probes out of range");
@@ -712,6 +715,26 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
   TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
   TRY(check_flags_and_finish(ctx, n_events));
   TRY(copy_moments_out(ctx, n_terms, moments_out));
+  ctx->mom_p = n_terms;
+  return RFO_OK;
+}
+
+int rfo_traces_at(rfo_ctx *ctx, double T, double mu, double *NEF_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (ctx->mom_p < 1) return fail(ctx, RFO_E_STATE, "no moments: call rfo_fermi_moments first");
+  if (!NEF_out) return fail(ctx, RFO_E_INVALID, "NEF_out is NULL");
+  if (!(T > 0.0) || !std::isfinite(T)) return fail(ctx, RFO_E_INVALID, "T must be finite and > 0");
+  if (!std::isfinite(mu)) return fail(ctx, RFO_E_INVALID, "mu must be finite");
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t p = ctx->mom_p, nq = 4 * p;
+  HIPCHK(rfo::launch_coefficients(ctx->e_min, ctx->e_max, T, mu, p, nq, P<double>(ctx->samples),
+                                  P<double>(ctx->costab), P<double>(ctx->coef), ctx->stream));
+  double *obs = P<double>(ctx->small);
+  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
+                            ctx->sp, obs, ctx->stream));
+  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return RFO_OK;
 }
 
@@ -869,6 +892,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
   TRY(check_flags_and_finish(ctx, n_events));
   ctx->has_grad = true;
+  ctx->mom_p = p;
   return RFO_OK;
 }
 
@@ -1013,6 +1037,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
   TRY(check_flags_and_finish(ctx, n_events));
   ctx->has_grad = true;
+  ctx->mom_p = p;
   return RFO_OK;
 }
 

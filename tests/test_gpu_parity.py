@@ -92,6 +92,31 @@ def test_doubling_short_series_and_direct_path(bd):
         assert abs(g["F"] - d["F"]) <= 1e-12 * abs(d["F"]), p
 
 
+def test_traces_at_other_T_mu_and_mu_search():
+    """The moments do not depend on (T, mu): traces at a new (T, mu) from the
+    stored moments equal a fresh call there and the oracle; bisection on them
+    recovers the mu of a given electron count."""
+    banner("traces_at and mu search")
+    import paper_1812_05264_amd as pkg
+    eng = engine_or_skip()
+    H = cu_cluster(55, config_id=22).bsr()
+    R = rademacher(H.n, 100, config_id=503)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    with pytest.raises(pkg.RfoError):
+        eng.traces_at(0.2, 0.0)                     # no moments yet
+    p = 200
+    eng.fermi_moments(0.3, 0.5, p, moments=True)
+    t = eng.traces_at(0.2, -0.4)
+    d = eng.fermi_moments(0.2, -0.4, p)
+    o = est.estimate(H, R, 0.2, -0.4, p)
+    for key in ("N", "E", "F"):
+        assert abs(t[key] - d[key]) <= 1e-13 * max(1.0, abs(d[key])), key
+        assert abs(t[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
+    mu = pkg.find_mu(eng, o["N"], 0.2, -5.0, 5.0, tol=1e-11)
+    assert abs(mu + 0.4) < 1e-7
+
+
 def test_config_sc8_against_closed_form():
     # the simple-cubic config: estimate within ~5 sigma of the exact band, trace identities exact
     banner("sc8 closed form")
