@@ -6,5 +6,7 @@ its ctypes binding and a torch.autograd.Function around the free-energy gradient
 
 from ._rfo import Engine, RfoError, library_path, load, PRECISIONS  # noqa: F401
 from .scan import find_mu  # noqa: F401
+from .colored import colored_probes, welsh_powell  # noqa: F401
 
-__all__ = ["Engine", "RfoError", "library_path", "load", "PRECISIONS", "find_mu"]
+__all__ = ["Engine", "RfoError", "library_path", "load", "PRECISIONS", "find_mu",
+           "colored_probes", "welsh_powell"]

@@ -1,0 +1,65 @@
+"""Multi-color probe ensemble on the GPU (Hybrid approximation, multi-color
+vector ensemble): the structured +-1/0 probes go through the same probe input,
+so moments, density, gradient and forces must match the oracle on the same
+probes, and the estimate's error must be exactly the same-colour sum of the
+truncated density matrix."""
+
+import numpy as np
+import pytest
+
+from oracle import estimator as est
+from oracle import forces as ofo
+from oracle import trunc
+from tests.gpu_common import TOL, banner, engine_or_skip, load_hamiltonian, rel
+from workloads import cu_cluster, rademacher_signs
+
+pytestmark = pytest.mark.gpu
+
+
+def colored(cl, r_max, config_id):
+    from paper_1812_05264_amd.colored import colored_probes, welsh_powell
+    c = welsh_powell(cl.positions, r_max)
+    return colored_probes(c, 9, rademacher_signs(cl.n_atoms, 9, config_id=config_id))
+
+
+@pytest.mark.parametrize("doubling", [True, False])
+def test_colored_probes_match_oracle(doubling):
+    banner(f"multi-color probes vs oracle doubling={doubling}")
+    eng = engine_or_skip()
+    eng.set_moment_doubling(doubling)
+    cl = cu_cluster(55, config_id=44)
+    H = cl.bsr()
+    R, w = colored(cl, 4.5, 44)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R, w)
+    T, mu, p = 0.3, 0.3, 90
+    g = eng.fermi_moments(T, mu, p, moments=True, density=True)
+    o = est.estimate(H, R, T, mu, p, weights=w, density=True, gradient=True)
+    assert rel(g["moments"], o["moments"]) < TOL
+    assert rel(g["density"], o["density"]) < TOL
+    for key in ("N", "E", "F"):
+        assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
+    e = eng.energy_and_dEdH(T, mu, p)
+    assert rel(e["dFdH"], o["dFdH"]) < TOL
+    D = cl.dH_dR()
+    assert rel(eng.hf_forces(D), ofo.hf_forces(H, o["dFdH"], D)) < TOL
+
+
+def test_colored_error_is_the_same_colour_sum():
+    banner("multi-color error structure vs coloring radius")
+    eng = engine_or_skip()
+    cl = cu_cluster(201, config_id=45)
+    H = cl.bsr()
+    load_hamiltonian(eng, H)
+    T, mu, p = 0.3, 0.3, 120
+    P = trunc.observables(H.to_dense(), H.e_min, H.e_max, T, mu, p)["P"]
+    errs = []
+    for r_max in (3.0, 6.0, 9.0):
+        R, w = colored(cl, r_max, 45)
+        eng.set_probes(R, w)
+        g = eng.fermi_moments(T, mu, p)
+        E = R @ R.T - np.eye(R.shape[0])
+        err = g["N"] - np.trace(P)
+        assert abs(err - np.sum(P * E)) < 1e-9 * np.trace(P), r_max
+        errs.append((r_max, R.shape[1], err))
+    print("coloring radius, probe columns, N error:", errs)

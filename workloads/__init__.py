@@ -16,7 +16,7 @@ from .bsr import BSR
 from .lattice import simple_cubic
 from .graph import random_graph
 from .cluster import CuCluster, cu_cluster
-from .probes import rademacher, identity_probes
+from .probes import rademacher, identity_probes, rademacher_signs
 from .configs import CONFIGS, get_config
 
 __all__ = [
@@ -26,6 +26,7 @@ __all__ = [
     "CuCluster",
     "cu_cluster",
     "rademacher",
+    "rademacher_signs",
     "identity_probes",
     "CONFIGS",
     "get_config",

@@ -16,3 +16,9 @@ def rademacher(n: int, s: int, config_id: int = 0, stream: int = 1) -> np.ndarra
 
 def identity_probes(n: int) -> np.ndarray:
     return np.eye(n, dtype=np.float64)
+
+
+def rademacher_signs(n_atoms: int, n_orb: int, config_id: int = 0, stream: int = 5) -> np.ndarray:
+    """Random +-1 phases [n_atoms, n_orb] for a structured (multi-color) probe block."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([20181205, config_id, stream])))
+    return 2.0 * rng.integers(0, 2, size=(n_atoms, n_orb)).astype(np.float64) - 1.0
