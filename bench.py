@@ -19,7 +19,9 @@ Also reported on the same line:
   energy_force  energy + gradient + Hellmann-Feynman forces on the 16,000-atom
                 Cu-like cluster (8000 terms, 256 probes), FP64 and FP32 with the
                 doubled moments (the library default), and FP64 with the direct
-                recurrence, with the errors against the FP64 doubled result per atom
+                recurrence, with the errors against the FP64 doubled result per atom;
+                and FP64 with a multi-color probe ensemble (one sample, coloring
+                radius 6 A) in place of the 256 Rademacher probes
 """
 
 import argparse
@@ -124,6 +126,30 @@ def energy_force(args):
         print(f"[bench] energy_force {key}: {dt:.3f} s  F={g['F']:.6f} E={g['E']:.6f}", flush=True)
         eng.close()
         del eng
+    if args.ef_colored > 0:
+        # multi-color probe ensemble (one sample, weights 1) at coloring radius ef_colored
+        from workloads import rademacher_signs
+        colours = pkg.welsh_powell(cl.positions, args.ef_colored)
+        Rc, wc = pkg.colored_probes(colours, 9, rademacher_signs(cl.n_atoms, 9, config_id=cfg.config_id))
+        eng = pkg.Engine(0)
+        eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, "fp64")
+        eng.set_probes(Rc, wc)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = eng.energy_and_dEdH(cfg.T, cfg.mu, n_terms, gradient=False)
+        f = eng.hf_forces(D)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        eng.close()
+        del eng
+        out["colored"] = {"radius_A": args.ef_colored, "colours": int(colours.max()) + 1,
+                          "probe_columns": int(Rc.shape[1]), "seconds_fp64": round(dt, 4),
+                          "F_eV": g["F"]}
+        if "fp64" in res:
+            _, g64, f64 = res["fp64"]
+            out["colored"]["dF_eV_per_atom_vs_rademacher"] = abs(g["F"] - g64["F"]) / cl.n_atoms
+            out["colored"]["force_rms_vs_rademacher_eV_per_A"] = float(np.sqrt(np.mean((f - f64) ** 2)))
+        print(f"[bench] energy_force colored r={args.ef_colored} ({Rc.shape[1]} columns): {dt:.3f} s", flush=True)
     if "fp64" in res:
         _, g64, f64 = res["fp64"]
         for prec, (dt, g, f) in res.items():
@@ -150,6 +176,8 @@ def main():
     ap.add_argument("--ef-precisions", default="fp64,fp32")
     ap.add_argument("--ef-direct", type=int, default=1,
                     help="also time FP64 energy_force with the direct recurrence (no doubling)")
+    ap.add_argument("--ef-colored", type=float, default=6.0,
+                    help="coloring radius (A) of a multi-color probe energy_force run (0 = skip)")
     ap.add_argument("--ef-terms", type=int, default=0,
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
