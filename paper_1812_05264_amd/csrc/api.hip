@@ -647,7 +647,9 @@ int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R, const double
   HIPCHK(hipSetDevice(ctx->device));
   ctx->has_r = false;
   ctx->has_grad = false;
-  const int sp = (int)((n_probes + 63) / 64 * 64);
+  // padded probe count: a multiple of 64, and of 128 above 64 probes so that FP64
+  // waves can take 2 probes per lane (16 B loads); padding probes have weight 0
+  const int sp = n_probes <= 64 ? 64 : (int)((n_probes + 127) / 128 * 128);
   const size_t n = (size_t)ctx->n;
   TRY(ensure(ctx, ctx->rden, n * sp * sizeof(double)));
   TRY(ensure(ctx, ctx->sgn, n * (sp / 64) * sizeof(uint64_t)));
