@@ -156,6 +156,41 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
  * Errors: RFO_E_STATE before rfo_energy_and_dEdH. */
 int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out);
 
+/* Nonorthogonal basis (paper: Polynomial approximation with S, Eq. poly_PQ).
+ * values [nnzb][bd][bd] FP64 (host or device): the overlap S on H's block
+ * pattern, symmetric positive definite; NULL clears it (S = I).  With S set,
+ * H_hat = [2H - (e_max + e_min) S]/(e_max - e_min) and every step forms
+ * y_{k+1} = 2 H_hat S^{-1} y_k - y_{k-1}, applying S^{-1} to every probe column
+ * by conjugate gradients to |residual| <= cg_tol |y| (cg_tol <= 0: 1e-13).  The
+ * moments stay mu_k = r . y_k (N = tr[P S]); with density output the library
+ * also forms the Q blocks (Q y = S^{-1} H S^{-1} sum_k alpha_k y_k).  Moment
+ * doubling is not used (T_k(H_hat S^{-1}) is not symmetric) and
+ * rfo_energy_and_dEdH returns RFO_E_UNSUPPORTED while S is set.
+ * Requires FP64 precision and an interval passed to rfo_set_hamiltonian that
+ * contains the spectrum of the pencil (H, S) (RFO_E_UNSUPPORTED / RFO_E_STATE
+ * otherwise).  rfo_set_hamiltonian clears S.
+ * Errors: RFO_E_NUMERIC for non-finite values or a CG that breaks down or does
+ * not converge (S not positive definite), RFO_E_INVALID for S_JI != S_IJ^T. */
+int rfo_set_overlap(rfo_ctx *ctx, const double *values, double cg_tol);
+
+/* Q blocks [nnzb][bd][bd] of the last rfo_fermi_moments call with density and
+ * an overlap (host or device memory).  RFO_E_STATE otherwise. */
+int rfo_get_density_q(rfo_ctx *ctx, double *q_out);
+
+/* Forces from the density blocks of the last rfo_fermi_moments call with
+ * density (paper: Observable response): for a two-centre model with
+ * dHdR, dSdR [nnzb][3][bd][bd] = d H_IJ / d R_I, d S_IJ / d R_I,
+ *   force_a = -(tr[P dH/dR_a] - tr[Q dS/dR_a])
+ * with the estimated P and Q blocks (dSdR NULL: no overlap term).
+ * forces_out [n_block_rows][3].  Unlike rfo_hf_forces these are the forces of
+ * the density estimate, not the gradient of F~.
+ * Errors: RFO_E_STATE without density blocks, or dSdR without Q blocks. */
+int rfo_density_forces(rfo_ctx *ctx, const double *dHdR, const double *dSdR,
+                       double *forces_out);
+
+/* Conjugate-gradient iterations and solves since the context was created. */
+int rfo_cg_stats(const rfo_ctx *ctx, int64_t *iterations, int64_t *solves);
+
 /* Moment doubling for calls without density output (see rfo_fermi_moments):
  * enabled != 0 turns it on (the default), 0 makes every moment a direct
  * r . y_k over p - 1 steps. */

@@ -56,10 +56,15 @@ def load():
     lib.rfo_set_timing.argtypes = [vp, i32]
     lib.rfo_set_moment_doubling.argtypes = [vp, i32]
     lib.rfo_traces_at.argtypes = [vp, dbl, dbl, ctypes.POINTER(dbl)]
+    lib.rfo_set_overlap.argtypes = [vp, vp, dbl]
+    lib.rfo_get_density_q.argtypes = [vp, vp]
+    lib.rfo_density_forces.argtypes = [vp, vp, vp, vp]
+    lib.rfo_cg_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rfo_step_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     for f in ("rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
               "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing",
-              "rfo_step_timing", "rfo_set_moment_doubling", "rfo_traces_at"):
+              "rfo_step_timing", "rfo_set_moment_doubling", "rfo_traces_at", "rfo_set_overlap",
+              "rfo_get_density_q", "rfo_density_forces", "rfo_cg_stats"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -201,6 +206,30 @@ class Engine:
         return out
 
     # -- instrumentation --------------------------------------------------------------
+    def set_overlap(self, S_values=None, cg_tol=1e-13):
+        """Overlap S [nnzb, bd, bd] on H's pattern (None: S = I)."""
+        S = None if S_values is None else _host(S_values, np.float64)
+        self._check(self._lib.rfo_set_overlap(self._ctx, _ptr(S), float(cg_tol)))
+
+    def density_q(self):
+        """Q blocks of the last fermi_moments call with density and an overlap."""
+        out = np.empty((self.nnzb, self.block_dim, self.block_dim))
+        self._check(self._lib.rfo_get_density_q(self._ctx, _ptr(out)))
+        return out
+
+    def density_forces(self, dHdR, dSdR=None):
+        """-(tr[P dH/dR_a] - tr[Q dS/dR_a]) from the last density blocks, [n_block_rows, 3]."""
+        dH = _host(dHdR, np.float64)
+        dS = None if dSdR is None else _host(dSdR, np.float64)
+        out = np.empty((self.n_block_rows, 3))
+        self._check(self._lib.rfo_density_forces(self._ctx, _ptr(dH), _ptr(dS), _ptr(out)))
+        return out
+
+    def cg_stats(self):
+        it, so = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.rfo_cg_stats(self._ctx, ctypes.byref(it), ctypes.byref(so)))
+        return it.value, so.value
+
     def traces_at(self, T, mu):
         """N, E, F at (T, mu) from the moments of the last fermi_moments / energy call."""
         out = (ctypes.c_double * 3)()

@@ -51,6 +51,12 @@ struct rfo_ctx {
   bool has_grad = false;
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
+  // nonorthogonal basis: overlap S on H's pattern, S^{-1} by conjugate gradients
+  bool has_s = false, interval_given = false, has_q = false, has_dens = false;
+  double cg_tol = 1e-13;
+  DevBuf s64, cg_part, cg_sc, GQ;
+  double *cg_res_h = nullptr;
+  int64_t cg_iters = 0, cg_solves = 0;
   int64_t mom_p = 0;     // moments of the last call still valid on the device (0 = none)
 
   // instrumentation
@@ -63,12 +69,14 @@ struct rfo_ctx {
   ~rfo_ctx() {
     hipSetDevice(device);
     DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch, &nz_up, &nz_low,
+                     &s64, &cg_part, &cg_sc, &GQ,
                      &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
                      &costab, &small, &flags, &G, &dHdR, &forces};
     for (DevBuf *b : all)
       if (b->p) hipFree(b->p);
     for (hipEvent_t e : events) hipEventDestroy(e);
     if (flags_h) hipHostFree(flags_h);
+    if (cg_res_h) hipHostFree(cg_res_h);
   }
 };
 
@@ -289,6 +297,55 @@ struct Checkpoints {
   DevBuf *store = nullptr;  // 2 (Q - 1) vectors: [q-1][0] = y_{qm-1}, [q-1][1] = y_{qm}
 };
 
+int ensure_cg(rfo_ctx *ctx) {
+  TRY(ensure(ctx, ctx->cg_part, (size_t)rfo::cg_nparts(ctx->n) * ctx->sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->cg_sc, ((size_t)6 * ctx->sp + 1) * sizeof(double)));
+  if (!ctx->cg_res_h) HIPCHK(hipHostMalloc((void **)&ctx->cg_res_h, sizeof(double), 0));
+  return RFO_OK;
+}
+
+// t = S^{-1} y for every probe column by conjugate gradients (S symmetric positive
+// definite), to |r_c| <= cg_tol |y_c|.  Work vectors: slots 3..5 of bufs.
+int cg_solve(rfo_ctx *ctx, const Plan &pl, DevBuf &bufs, const void *y, void *t) {
+  const int64_t n = ctx->n;
+  const int sp = ctx->sp;
+  double *r = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 3));
+  double *pv = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 4));
+  double *q = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 5));
+  double *part = P<double>(ctx->cg_part), *sc = P<double>(ctx->cg_sc);
+  double *res_d = sc + 6 * sp;
+  HIPCHK(rfo::launch_cg_init(static_cast<const double *>(y), static_cast<double *>(t), r, pv, n, sp,
+                             part, sc, ctx->stream));
+  rfo::StepArgs sa;
+  fill_step(ctx, pl, sa);
+  sa.hval = ctx->s64.p;  // q = S p
+  sa.x = pv;
+  sa.prev = nullptr;
+  sa.out = q;
+  sa.c1 = 1.0;
+  sa.c2 = 0.0;
+  const double tol2 = ctx->cg_tol * ctx->cg_tol;
+  const int max_it = 2000;
+  for (int it = 1; it <= max_it; ++it) {
+    HIPCHK(launch_any_step(ctx, pl, sa));
+    HIPCHK(rfo::launch_cg_alpha(pv, q, n, sp, part, sc, ctx->stream));
+    HIPCHK(rfo::launch_cg_update(static_cast<double *>(t), r, pv, q, n, sp, part, sc, res_d,
+                                 ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->cg_res_h, res_d, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    ++ctx->cg_iters;
+    const double res = *ctx->cg_res_h;
+    if (!std::isfinite(res))
+      return fail(ctx, RFO_E_NUMERIC, "conjugate gradients broke down: S is not positive definite");
+    if (res <= tol2) {
+      ++ctx->cg_solves;
+      return RFO_OK;
+    }
+  }
+  return fail(ctx, RFO_E_NUMERIC, "conjugate gradients did not reach %g in %d iterations", ctx->cg_tol,
+              max_it);
+}
+
 int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_acc,
                 const Checkpoints *ck, size_t *n_events, bool dbl = false) {
   if (dbl && use_acc) return fail(ctx, RFO_E_INVALID, "the density needs every y_k");
@@ -359,12 +416,19 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
     // pass (y_{k-1}, y_k, y_{k+1}) or at the last step
     const int64_t pending = k + 1 - acc_done;
     sa.acc = accp;
-    sa.acc_terms = (accp && (pending == 3 || k + 2 == p)) ? (int)pending : 0;
+    // with an overlap the pass gathers t_k = S^{-1} y_k, not y_k: one term per pass
+    sa.acc_terms = (accp && (ctx->has_s || pending == 3 || k + 2 == p)) ? (int)pending : 0;
     sa.alpha = coef + (acc_done + 1);
     if (sa.acc_terms) acc_done = k + 1;
     const int64_t hi = dbl ? 2 * (k + 1) : k + 1;  // highest moment index of this step
     sa.part = ring + (size_t)(hi % pl.ring) * slot;
     sa.part2 = dbl ? ring + (size_t)((hi - 1) % pl.ring) * slot : nullptr;
+    if (ctx->has_s) {
+      // y_{k+1} = 2 H_hat S^{-1} y_k - y_{k-1}: gather t_k = S^{-1} y_k (slot 2)
+      char *t = vec_at(ctx, pl, bufs, 2);
+      TRY(cg_solve(ctx, pl, bufs, cur, t));
+      sa.x = t;
+    }
     HIPCHK(launch_any_step(ctx, pl, sa));
     prev = cur;
     cur = out;
@@ -381,8 +445,8 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
       }
       const int64_t last = std::min(hi, p - 1);
       HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, batch_start, (int)(last - batch_start + 1),
-                                       pl.grid, ctx->sp, mom, 1, tol, flags, dbl ? 1 : 0,
-                                       ctx->stream));
+                                       pl.grid, ctx->sp, mom, ctx->has_s ? 0 : 1, tol, flags,
+                                       dbl ? 1 : 0, ctx->stream));
       batch_start = last + 1;
       batch_steps = 0;
     }
@@ -575,7 +639,10 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
   ctx->has_grad = false;
   const size_t nval = (size_t)ctx->nnzb * ctx->bd * ctx->bd;
   const size_t npad = (size_t)rfo::kStepPad * ctx->bd * ctx->bd;
-  TRY(ensure(ctx, ctx->hraw, nval * sizeof(double)));
+  // H_hat, S and the unmapped H all carry kStepPad zero blocks: the 9x9 step
+  // reads whole chunks of blocks
+  TRY(ensure(ctx, ctx->hraw, (nval + npad) * sizeof(double)));
+  HIPCHK(hipMemsetAsync(P<double>(ctx->hraw) + nval, 0, npad * sizeof(double), ctx->stream));
   TRY(ensure(ctx, ctx->h64, (nval + npad) * sizeof(double)));
   HIPCHK(hipMemsetAsync(P<double>(ctx->h64) + nval, 0, npad * sizeof(double), ctx->stream));
   if (precision == RFO_FP32) {
@@ -590,6 +657,10 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
   }
   HIPCHK(hipMemcpyAsync(ctx->hraw.p, values, nval * sizeof(double), hipMemcpyDefault, ctx->stream));
 
+  ctx->has_s = false;  // a new H drops the overlap (set it again after this call)
+  ctx->has_q = false;
+  ctx->has_dens = false;
+  ctx->interval_given = e_min < e_max;
   if (e_min >= e_max) {
     const int nblk = (int)((ctx->n + rfo::kWG - 1) / rfo::kWG);
     TRY(ensure(ctx, ctx->gscratch, (size_t)2 * nblk * sizeof(double)));
@@ -638,6 +709,8 @@ int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R, const double
   if (!ctx) return RFO_E_INVALID;
   ctx->err.clear();
   ctx->mom_p = 0;
+  ctx->has_dens = false;
+  ctx->has_q = false;
   if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "set the Hamiltonian before the probes");
   if (!R) return fail(ctx, RFO_E_INVALID, "R is NULL");
   if (n_probes < 1 || n_probes > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_probes out of range");
@@ -681,15 +754,38 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
   Plan pl;
   TRY(prepare_call(ctx, T, mu, n_terms, pl));
   const bool dens = density_out != nullptr;
-  TRY(ensure(ctx, ctx->vec, 2 * pl.vec_elems * pl.vt_bytes));
+  // vector slots: y pair; with an overlap also t and the CG vectors r, p, q
+  TRY(ensure(ctx, ctx->vec, (ctx->has_s ? 6 : 2) * pl.vec_elems * pl.vt_bytes));
   if (dens) TRY(ensure(ctx, ctx->acc, pl.vec_elems * pl.vt_bytes));
+  if (ctx->has_s) TRY(ensure_cg(ctx));
   size_t n_events = 0;
-  TRY(run_forward(ctx, pl, n_terms, ctx->vec, dens, nullptr, &n_events, !dens && ctx->doubling));
+  TRY(run_forward(ctx, pl, n_terms, ctx->vec, dens, nullptr, &n_events,
+                  !dens && ctx->doubling && !ctx->has_s));
   double *obs = P<double>(ctx->small);
   HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef),
                             n_terms, ctx->sp, obs, ctx->stream));
+  ctx->has_q = false;
+  ctx->has_dens = false;
   if (dens) {
     TRY(ensure(ctx, ctx->G, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
+    // P r = S^{-1} acc and Q r = S^{-1} H S^{-1} acc with an overlap (Eq. poly_PQ)
+    void *px = ctx->acc.p, *qx = nullptr;
+    if (ctx->has_s) {
+      px = vec_at(ctx, pl, ctx->vec, 2);
+      TRY(cg_solve(ctx, pl, ctx->vec, ctx->acc.p, px));
+      rfo::StepArgs sa;
+      fill_step(ctx, pl, sa);
+      sa.hval = ctx->hraw.p;  // v = H u with the unmapped Hamiltonian
+      sa.x = px;
+      sa.prev = nullptr;
+      sa.out = vec_at(ctx, pl, ctx->vec, 0);
+      sa.c1 = 1.0;
+      sa.c2 = 0.0;
+      HIPCHK(launch_any_step(ctx, pl, sa));
+      qx = vec_at(ctx, pl, ctx->vec, 1);
+      TRY(cg_solve(ctx, pl, ctx->vec, vec_at(ctx, pl, ctx->vec, 0), qx));
+      TRY(ensure(ctx, ctx->GQ, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
+    }
     rfo::SddmmArgs a;
     memset(&a, 0, sizeof(a));
     a.brow = P<int64_t>(ctx->brow);
@@ -697,7 +793,7 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
     a.nnzb = ctx->nnzb;
     a.bd = ctx->bd;
     a.sp = ctx->sp;
-    a.xbase = ctx->acc.p;
+    a.xbase = px;
     a.ybase = nullptr;
     a.sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
     a.rden = ctx->signs ? nullptr : P<double>(ctx->rden);
@@ -711,7 +807,14 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
     a.nzlist = nullptr;
     a.ppl = sddmm_ppl(ctx);
     HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
+    if (qx) {
+      a.xbase = qx;
+      a.G = P<double>(ctx->GQ);
+      HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
+      ctx->has_q = true;
+    }
     ctx->has_grad = false;  // G now holds the density
+    ctx->has_dens = true;
     TRY(copy_out(ctx, density_out, ctx->G.p, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
   }
   TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
@@ -894,6 +997,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
   TRY(check_flags_and_finish(ctx, n_events));
   ctx->has_grad = true;
+  ctx->has_dens = false;
   ctx->mom_p = p;
   return RFO_OK;
 }
@@ -905,6 +1009,10 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   Plan pl;
   TRY(prepare_call(ctx, T, mu, n_terms, pl));
   const int64_t p = n_terms;
+  if (ctx->has_s)
+    return fail(ctx, RFO_E_UNSUPPORTED,
+                "the free-energy gradient with an overlap is not implemented; use the density "
+                "blocks and rfo_density_forces");
   if (ctx->doubling && p >= 2) {
     TRY(ensure(ctx, ctx->G, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
     ctx->has_grad = false;
@@ -1039,6 +1147,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
   TRY(check_flags_and_finish(ctx, n_events));
   ctx->has_grad = true;
+  ctx->has_dens = false;
   ctx->mom_p = p;
   return RFO_OK;
 }
@@ -1054,10 +1163,99 @@ int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out) {
   TRY(ensure(ctx, ctx->forces, (size_t)ctx->nb * 3 * sizeof(double)));
   HIPCHK(hipMemcpyAsync(ctx->dHdR.p, dHdR, dbytes, hipMemcpyDefault, ctx->stream));
   HIPCHK(rfo::launch_forces(P<int64_t>(ctx->row_ptr), P<int64_t>(ctx->tpos), P<double>(ctx->G),
-                            P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces),
+                            P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces), 1.0, 0,
                             ctx->stream));
   TRY(copy_out(ctx, forces_out, ctx->forces.p, (size_t)ctx->nb * 3 * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_set_overlap(rfo_ctx *ctx, const double *values, double cg_tol) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "set the Hamiltonian before the overlap");
+  HIPCHK(hipSetDevice(ctx->device));
+  ctx->mom_p = 0;
+  ctx->has_q = false;
+  ctx->has_grad = false;
+  ctx->has_dens = false;
+  if (!values) {  // back to S = I: the plain map of H
+    ctx->has_s = false;
+    HIPCHK(hipMemsetAsync(ctx->flags.p, 0, sizeof(int), ctx->stream));
+    HIPCHK(rfo::launch_map(P<double>(ctx->hraw), P<int64_t>(ctx->brow), P<int32_t>(ctx->col),
+                           P<int64_t>(ctx->tpos), ctx->nnzb, ctx->bd, ctx->e_min, ctx->e_max,
+                           P<double>(ctx->h64), nullptr, P<int>(ctx->flags), ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    return RFO_OK;
+  }
+  if (ctx->prec != RFO_FP64)
+    return fail(ctx, RFO_E_UNSUPPORTED, "an overlap needs FP64 precision");
+  if (!ctx->interval_given)
+    return fail(ctx, RFO_E_STATE,
+                "with an overlap pass the spectral interval of the pencil (H, S) to "
+                "rfo_set_hamiltonian (the Gershgorin fallback bounds H alone)");
+  if (!(cg_tol > 0.0) || !(cg_tol < 1.0)) cg_tol = 1e-13;
+  const size_t nval = (size_t)ctx->nnzb * ctx->bd * ctx->bd;
+  const size_t npad = (size_t)rfo::kStepPad * ctx->bd * ctx->bd;
+  TRY(ensure(ctx, ctx->s64, (nval + npad) * sizeof(double)));
+  HIPCHK(hipMemsetAsync(P<double>(ctx->s64) + nval, 0, npad * sizeof(double), ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->s64.p, values, nval * sizeof(double), hipMemcpyDefault, ctx->stream));
+  HIPCHK(hipMemsetAsync(ctx->flags.p, 0, sizeof(int), ctx->stream));
+  HIPCHK(rfo::launch_map_overlap(P<double>(ctx->hraw), P<double>(ctx->s64), P<int64_t>(ctx->tpos),
+                                 ctx->nnzb, ctx->bd, ctx->e_min, ctx->e_max, P<double>(ctx->h64),
+                                 P<int>(ctx->flags), ctx->stream));
+  HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (*ctx->flags_h & 1) return fail(ctx, RFO_E_NUMERIC, "non-finite overlap values");
+  if (*ctx->flags_h & 2) return fail(ctx, RFO_E_INVALID, "overlap values are not symmetric (S_JI != S_IJ^T)");
+  ctx->has_s = true;
+  ctx->cg_tol = cg_tol;
+  return RFO_OK;
+}
+
+int rfo_get_density_q(rfo_ctx *ctx, double *q_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_q)
+    return fail(ctx, RFO_E_STATE, "no Q blocks: call rfo_fermi_moments with density and an overlap");
+  if (!q_out) return fail(ctx, RFO_E_INVALID, "q_out is NULL");
+  TRY(copy_out(ctx, q_out, ctx->GQ.p, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_density_forces(rfo_ctx *ctx, const double *dHdR, const double *dSdR, double *forces_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!dHdR || !forces_out) return fail(ctx, RFO_E_INVALID, "NULL argument");
+  if (!ctx->has_dens)
+    return fail(ctx, RFO_E_STATE, "no density blocks: call rfo_fermi_moments with density first");
+  if (dSdR && !ctx->has_q)
+    return fail(ctx, RFO_E_STATE, "no Q blocks: the last call had no overlap");
+  HIPCHK(hipSetDevice(ctx->device));
+  const size_t dbytes = (size_t)ctx->nnzb * 3 * ctx->bd * ctx->bd * sizeof(double);
+  TRY(ensure(ctx, ctx->dHdR, dbytes));
+  TRY(ensure(ctx, ctx->forces, (size_t)ctx->nb * 3 * sizeof(double)));
+  HIPCHK(hipMemcpyAsync(ctx->dHdR.p, dHdR, dbytes, hipMemcpyDefault, ctx->stream));
+  // force_a = -(tr[P dH/dR_a] - tr[Q dS/dR_a]) (Observable response)
+  HIPCHK(rfo::launch_forces(P<int64_t>(ctx->row_ptr), P<int64_t>(ctx->tpos), P<double>(ctx->G),
+                            P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces), 1.0, 0,
+                            ctx->stream));
+  if (dSdR) {
+    HIPCHK(hipMemcpyAsync(ctx->dHdR.p, dSdR, dbytes, hipMemcpyDefault, ctx->stream));
+    HIPCHK(rfo::launch_forces(P<int64_t>(ctx->row_ptr), P<int64_t>(ctx->tpos), P<double>(ctx->GQ),
+                              P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces), -1.0, 1,
+                              ctx->stream));
+  }
+  TRY(copy_out(ctx, forces_out, ctx->forces.p, (size_t)ctx->nb * 3 * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_cg_stats(const rfo_ctx *ctx, int64_t *iterations, int64_t *solves) {
+  if (!ctx || !iterations || !solves) return RFO_E_INVALID;
+  *iterations = ctx->cg_iters;
+  *solves = ctx->cg_solves;
   return RFO_OK;
 }
 

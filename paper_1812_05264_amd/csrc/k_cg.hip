@@ -1,0 +1,202 @@
+// Nonorthogonal basis (paper: Polynomial approximation with S, Eq. poly_PQ):
+// the mapped Hamiltonian H_hat = [2H - (e_max + e_min) S]/(e_max - e_min) and
+// the pieces of a conjugate-gradient solve S t = y for a block of probe columns
+// (one independent CG per column; the matrix-vector product is the step kernel
+// with S as its matrix).  Column reductions are two-pass and in a fixed order.
+#include "device_util.h"
+#include "rfo_internal.h"
+
+namespace rfo {
+
+__global__ __launch_bounds__(kWG) void k_map_overlap(const double *__restrict__ h,
+                                                     const double *__restrict__ s,
+                                                     const int64_t *__restrict__ tpos,
+                                                     int64_t nnzb, int bd, double e_min,
+                                                     double e_max, double *__restrict__ hhat,
+                                                     int *flags) {
+  const int bb = bd * bd;
+  const int64_t total = nnzb * bb;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nz = e / bb;
+    const int rem = (int)(e - nz * bb);
+    const int i = rem / bd, j = rem - (rem / bd) * bd;
+    const double v = s[e];
+    if (!isfinite(v)) atomicOr(flags, 1);
+    const double vt = s[tpos[nz] * bb + j * bd + i];
+    if (!(fabs(v - vt) <= 1e-10 * (fabs(v) + fabs(vt)))) atomicOr(flags, 2);
+    hhat[e] = (2.0 * h[e] - (e_max + e_min) * v) / (e_max - e_min);
+  }
+}
+
+hipError_t launch_map_overlap(const double *h, const double *s, const int64_t *tpos, int64_t nnzb,
+                              int bd, double e_min, double e_max, double *hhat, int *flags,
+                              hipStream_t st) {
+  const int64_t total = nnzb * bd * bd;
+  int64_t blocks = (total + kWG - 1) / kWG;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_map_overlap, dim3((unsigned)blocks), dim3(kWG), 0, st, h, s, tpos, nnzb, bd,
+                     e_min, e_max, hhat, flags);
+  return hipGetLastError();
+}
+
+namespace {
+
+// rows [lo, hi) of workgroup b when n rows are split over gridDim.x workgroups
+__device__ __forceinline__ void row_range(int64_t n, int64_t &lo, int64_t &hi) {
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  lo = n * b / G;
+  hi = n * (b + 1) / G;
+}
+
+}  // namespace
+
+// part[b][c] = sum over this workgroup's rows of a[i][c] * b[i][c]
+__global__ __launch_bounds__(kWG) void k_coldot(const double *__restrict__ a,
+                                                const double *__restrict__ bv, int64_t n, int sp,
+                                                double *__restrict__ part) {
+  int64_t lo, hi;
+  row_range(n, lo, hi);
+  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; ++i) s = fma(a[i * sp + c], bv[i * sp + c], s);
+    part[(int64_t)blockIdx.x * sp + c] = s;
+  }
+}
+
+// out[c] = sum_b part[b][c], b in increasing order
+__global__ __launch_bounds__(kWG) void k_colreduce(const double *__restrict__ part, int nparts,
+                                                   int sp, double *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= sp) return;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * sp + c];
+  out[c] = s;
+}
+
+// t = 0, r = y, p = y, part = column partials of y . y
+__global__ __launch_bounds__(kWG) void k_cg_init(const double *__restrict__ y,
+                                                 double *__restrict__ t, double *__restrict__ r,
+                                                 double *__restrict__ p, int64_t n, int sp,
+                                                 double *__restrict__ part) {
+  int64_t lo, hi;
+  row_range(n, lo, hi);
+  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t e = i * sp + c;
+      const double v = y[e];
+      t[e] = 0.0;
+      r[e] = v;
+      p[e] = v;
+      s = fma(v, v, s);
+    }
+    part[(int64_t)blockIdx.x * sp + c] = s;
+  }
+}
+
+// t += alpha_c p, r -= alpha_c q, part = column partials of r . r
+__global__ __launch_bounds__(kWG) void k_cg_update(double *__restrict__ t, double *__restrict__ r,
+                                                   const double *__restrict__ p,
+                                                   const double *__restrict__ q,
+                                                   const double *__restrict__ alpha, int64_t n,
+                                                   int sp, double *__restrict__ part) {
+  int64_t lo, hi;
+  row_range(n, lo, hi);
+  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+    const double al = alpha[c];
+    double s = 0.0;
+    for (int64_t i = lo; i < hi; ++i) {
+      const int64_t e = i * sp + c;
+      t[e] = fma(al, p[e], t[e]);
+      const double rn = fma(-al, q[e], r[e]);
+      r[e] = rn;
+      s = fma(rn, rn, s);
+    }
+    part[(int64_t)blockIdx.x * sp + c] = s;
+  }
+}
+
+// p = r + beta_c p
+__global__ __launch_bounds__(kWG) void k_cg_direction(const double *__restrict__ r,
+                                                      double *__restrict__ p,
+                                                      const double *__restrict__ beta, int64_t n,
+                                                      int sp) {
+  const int64_t total = n * sp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = fma(beta[e % sp], p[e], r[e]);
+}
+
+// Per-column CG scalars (one workgroup).  sc = [yy | rr | pq | rrn | alpha | beta] of sp each.
+// mode 0: rr = yy (start);  mode 1: alpha = rr / pq;  mode 2: beta = rrn / rr, rr = rrn and
+// *resmax = max_c rrn / yy over columns with yy > 0 (columns with rr = 0 stay at alpha = beta = 0).
+__global__ __launch_bounds__(kWG) void k_cg_scalars(double *__restrict__ sc, int sp, int mode,
+                                                    double *__restrict__ resmax) {
+  double *yy = sc, *rr = sc + sp, *pq = sc + 2 * sp, *rrn = sc + 3 * sp, *al = sc + 4 * sp,
+         *be = sc + 5 * sp;
+  double m = 0.0;
+  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+    if (mode == 0) {
+      rr[c] = yy[c];
+    } else if (mode == 1) {
+      al[c] = (rr[c] > 0.0 && pq[c] != 0.0) ? rr[c] / pq[c] : 0.0;
+    } else {
+      be[c] = rr[c] > 0.0 ? rrn[c] / rr[c] : 0.0;
+      rr[c] = rrn[c];
+      if (yy[c] > 0.0) m = fmax(m, rrn[c] / yy[c]);
+    }
+  }
+  if (mode != 2) return;
+  m = wave_max(m);
+  __shared__ double red[kWaves];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = red[0];
+    for (int w = 1; w < kWaves; ++w) t = fmax(t, red[w]);
+    *resmax = t;
+  }
+}
+
+namespace {
+int cg_parts(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 63) / 64)); }
+}  // namespace
+
+int cg_nparts(int64_t n) { return cg_parts(n); }
+
+hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int64_t n, int sp,
+                          double *part, double *sc, hipStream_t s) {
+  const int G = cg_parts(n);
+  hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(kWG), 0, s, y, t, r, p, n, sp, part);
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, G, sp, sc);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 0, (double *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_alpha(const double *p, const double *q, int64_t n, int sp, double *part,
+                           double *sc, hipStream_t s) {
+  const int G = cg_parts(n);
+  hipLaunchKernelGGL(k_coldot, dim3(G), dim3(kWG), 0, s, p, q, n, sp, part);
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, G, sp,
+                     sc + 2 * sp);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 1, (double *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, int64_t n, int sp,
+                            double *part, double *sc, double *resmax, hipStream_t s) {
+  const int G = cg_parts(n);
+  hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kWG), 0, s, t, r, p, q, sc + 4 * sp, n, sp, part);
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, G, sp,
+                     sc + 3 * sp);
+  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 2, resmax);
+  int64_t blocks = (n * sp + kWG - 1) / kWG;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_cg_direction, dim3((unsigned)blocks), dim3(kWG), 0, s, r, p, sc + 5 * sp, n,
+                     sp);
+  return hipGetLastError();
+}
+
+}  // namespace rfo

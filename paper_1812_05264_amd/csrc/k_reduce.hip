@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kWG) void k_forces(const int64_t *__restrict__ row_
                                                 const int64_t *__restrict__ tpos,
                                                 const double *__restrict__ G,
                                                 const double *__restrict__ D, int64_t nb, int bd,
-                                                double *__restrict__ F) {
+                                                double *__restrict__ F, double sign, int accumulate) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t a = (int64_t)blockIdx.x * kWaves + wave;
@@ -169,16 +169,17 @@ __global__ __launch_bounds__(kWG) void k_forces(const int64_t *__restrict__ row_
   }
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    const double v = wave_sum(f[d]);
-    if (lane == 0) F[a * 3 + d] = -v;
+    const double v = -sign * wave_sum(f[d]);
+    if (lane == 0) F[a * 3 + d] = accumulate ? F[a * 3 + d] + v : v;
   }
 }
 
 hipError_t launch_forces(const int64_t *row_ptr, const int64_t *tpos, const double *G,
-                         const double *D, int64_t nb, int bd, double *F, hipStream_t s) {
+                         const double *D, int64_t nb, int bd, double *F, double sign, int accumulate,
+                         hipStream_t s) {
   if (nb == 0) return hipSuccess;
   hipLaunchKernelGGL(k_forces, dim3((unsigned)((nb + kWaves - 1) / kWaves)), dim3(kWG), 0, s,
-                     row_ptr, tpos, G, D, nb, bd, F);
+                     row_ptr, tpos, G, D, nb, bd, F, sign, accumulate);
   return hipGetLastError();
 }
 

@@ -154,9 +154,28 @@ hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s);
 // G[nz] = G[tpos[nz]]^T for the listed blocks (completes a symmetric gradient).
 hipError_t launch_mirror(const int64_t *nzlist, int64_t nlist, const int64_t *tpos, int bd,
                          double *G, hipStream_t s);
-// Hellmann-Feynman forces from G and d H_IJ / d R_I blocks.
+// Hellmann-Feynman forces from G and d H_IJ / d R_I blocks: F (+)= sign * force.
 hipError_t launch_forces(const int64_t *row_ptr, const int64_t *tpos,
                          const double *G, const double *D, int64_t nb, int bd,
-                         double *F, hipStream_t s);
+                         double *F, double sign, int accumulate, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Nonorthogonal basis: H_hat with S, and conjugate gradients for S t = y per
+// probe column.  sc holds [yy | rr | pq | rrn | alpha | beta] (sp each), part
+// [cg_nparts(n)][sp] column partials, resmax the largest rrn / yy after an update.
+// ---------------------------------------------------------------------------
+hipError_t launch_map_overlap(const double *h, const double *s, const int64_t *tpos, int64_t nnzb,
+                              int bd, double e_min, double e_max, double *hhat, int *flags,
+                              hipStream_t st);
+int cg_nparts(int64_t n);
+// t = 0, r = p = y, yy = rr = |y_c|^2
+hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int64_t n, int sp,
+                          double *part, double *sc, hipStream_t s);
+// alpha_c = rr_c / (p_c . q_c), q = S p computed before
+hipError_t launch_cg_alpha(const double *p, const double *q, int64_t n, int sp, double *part,
+                           double *sc, hipStream_t s);
+// t += alpha p, r -= alpha q, beta = |r|^2 / rr, rr = |r|^2, p = r + beta p, *resmax
+hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, int64_t n, int sp,
+                            double *part, double *sc, double *resmax, hipStream_t s);
 
 }  // namespace rfo
