@@ -22,6 +22,8 @@ Also reported on the same line:
                 recurrence, with the errors against the FP64 doubled result per atom;
                 and FP64 with a multi-color probe ensemble (one sample, coloring
                 radius 6 A) in place of the 256 Rademacher probes
+  overlap       the nonorthogonal basis (S^-1 by conjugate gradients in every step)
+                on the 4,000-atom cluster, 200 terms, moments and P, Q blocks
 """
 
 import argparse
@@ -164,6 +166,46 @@ def energy_force(args):
     return out
 
 
+def overlap_leg(args):
+    """Nonorthogonal basis: the 4,000-atom Cu-like cluster with the synthetic overlap
+    (condition number about 4.5), 128 Rademacher probes, moments and the P and Q
+    density blocks over ov_terms terms; every step applies S^-1 by conjugate
+    gradients (tolerance 1e-13).  The interval is the rigorous bound
+    max|spec H| / lambda_min(S)."""
+    import torch
+    import paper_1812_05264_amd as pkg
+    from workloads import cu_cluster, rademacher
+    from workloads.bsr import BSR
+    from workloads.overlap import overlap_values, pencil_bound
+    cl = cu_cluster(4000, config_id=2)
+    H = cl.bsr()
+    S = overlap_values(cl)
+    a, b = pencil_bound(H, S)
+    H = BSR(H.row_ptr, H.col_idx, H.values, 9, a, b)
+    R = rademacher(H.n, 128, config_id=2)
+    eng = pkg.Engine(0)
+    eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, a, b, "fp64")
+    eng.set_overlap(S, cg_tol=1e-13)
+    eng.set_probes(R)
+    eng.fermi_moments(0.05, 1.165, 8, density=True)
+    it0, so0 = eng.cg_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = eng.fermi_moments(0.05, 1.165, args.ov_terms, density=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it, so = eng.cg_stats()
+    eng.close()
+    out = {"workload": "cu4k with overlap", "atoms": cl.n_atoms, "probes": 128,
+           "n_terms": args.ov_terms, "interval_eV": [round(a, 4), round(b, 4)],
+           "seconds": round(dt, 4), "cg_solves": so - so0,
+           "cg_iterations_per_solve": round((it - it0) / max(1, so - so0), 2),
+           "ms_per_chebyshev_step": round(dt * 1e3 / max(1, args.ov_terms - 1), 3), "N": g["N"]}
+    print(f"[bench] overlap cu4k: {dt:.3f} s for {args.ov_terms} terms, "
+          f"{out['cg_iterations_per_solve']} CG iterations per solve", flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +220,8 @@ def main():
                     help="also time FP64 energy_force with the direct recurrence (no doubling)")
     ap.add_argument("--ef-colored", type=float, default=6.0,
                     help="coloring radius (A) of a multi-color probe energy_force run (0 = skip)")
+    ap.add_argument("--ov-terms", type=int, default=200,
+                    help="terms of the overlap (nonorthogonal basis) leg (0 = skip)")
     ap.add_argument("--ef-terms", type=int, default=0,
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
@@ -288,6 +332,9 @@ def main():
         del eng
         torch.cuda.empty_cache()
         line["energy_force"] = energy_force(args)
+    if args.ov_terms > 0:
+        torch.cuda.empty_cache()
+        line["overlap"] = overlap_leg(args)
     print(json.dumps(line), flush=True)
 
 

@@ -54,3 +54,16 @@ def pencil_interval(H, S_values, widen=0.01):
     ev = sl.eigh(H.to_dense(), S, eigvals_only=True)
     c, h = 0.5 * (ev[-1] + ev[0]), 0.5 * (ev[-1] - ev[0]) * (1.0 + widen)
     return c - h, c + h
+
+
+def pencil_bound(H, S_values, widen=0.01):
+    """A rigorous interval for the pencil (H, S) of a large system: for S-normalized
+    v, |v^T H v| / v^T S v <= max|spec H| / lambda_min(S); lambda_min(S) by sparse
+    Lanczos, max|spec H| from H's own interval.  Wider than the pencil's spectrum."""
+    import scipy.sparse.linalg as spla
+    S = H.with_values(S_values).to_scipy().tocsr()
+    lam = float(spla.eigsh(S, k=1, which="SA", tol=1e-6, return_eigenvectors=False)[0])
+    if not lam > 0.0:
+        raise ValueError("S is not positive definite")
+    r = max(abs(H.e_min), abs(H.e_max)) / (lam * (1.0 - 1e-4)) * (1.0 + widen)
+    return -r, r
