@@ -188,6 +188,57 @@ int rfo_get_density_q(rfo_ctx *ctx, double *q_out);
 int rfo_density_forces(rfo_ctx *ctx, const double *dHdR, const double *dSdR,
                        double *forces_out);
 
+/* Rational (pole) expansion, pole fit (paper: Rational approximation, Eq.
+ * rational_fit).  Host-only: needs no context and no GPU.  The paper's fastest
+ * fit is numerical and unprinted; this is the analytical kind it names for a
+ * finite spectral interval, applicable to both f and g: a trapezoid rule for a
+ * Cauchy integral on a conformal map of an annulus (Hale, Higham and Trefethen
+ * 2008), applied to the even parts of f and g as functions of (x - mu)^2.
+ * With n = n_nodes it returns 2n poles z_k, all with Im z_k > 0, shared by
+ *   f(x) ~ poly[0] + 2 Re sum_k res_f_k / (x - z_k),
+ *   g(x) ~ poly[1] + poly[2] x + 2 Re sum_k res_g_k / (x - z_k)
+ * on [e_min, e_max] (f = 2/(1 + exp((x - mu)/T)), g = -2T ln(1 + exp(-(x - mu)/T))).
+ * The error falls geometrically in n at a rate set by ln((e - mu)^2 / (pi T)^2).
+ *   poles, res_f, res_g: caller arrays of 2n complex numbers as (re, im) pairs
+ *   [2n][2]; poly: [3] = (f0, g0, g1).
+ * Errors: RFO_E_INVALID for n_nodes outside [1, 1024], T <= 0, e_max <= e_min,
+ * non-finite input or NULL; RFO_E_NUMERIC if a node evaluates to non-finite. */
+int rfo_rational_fit(int n_nodes, double T, double mu, double e_min, double e_max,
+                     double *poles, double *res_f, double *res_g, double *poly);
+
+/* Rational estimate with S = I (paper: Rational approximation, Eq. rational_PQ;
+ * rational free-energy primitive and its derivative, Eq. rational_derivative
+ * with dS = 0).  For every probe column the library solves the shifted systems
+ * (H - z_k) g_k = r_c by CGLS (conjugate gradients on the normal equations)
+ * to |r_c - (H - z_k) g_k| <= tol |r_c|, poles ordered by decreasing |z_k - mu|
+ * and each solve started from the previous pole's solution, and forms
+ *   P r = f0 r + 2 Re sum_k w_k g_k,
+ *   N = sum_c w_c r_c.P r_c,
+ *   E = sum_c w_c [f0 r_c.H r_c + 2 Re(sum_k w_k) r_c.r_c + 2 Re sum_k w_k z_k r_c.g_k],
+ *   F = sum_c w_c [g0 r_c.r_c + g1 r_c.H r_c + 2 Re sum_k tau_k r_c.g_k],
+ *   density  M (.) sum_c w_c (P r_c) r_c^T on H's block pattern,
+ *   dF/dH    g1 sum_c w_c r_c r_c^T - 2 Re sum_k tau_k sum_c w_c g_k g_k^T on the
+ *            pattern (G(z)^T = G(z) for symmetric H; no conjugation),
+ * with w_k = res_f, tau_k = res_g, (f0, g0, g1) = poly and w_c the probe weights.
+ *   mu: only orders the poles.  n_poles >= 1; poles, res_f, res_g [n_poles][2]
+ *   (re, im), host memory; every pole must have Im z_k > 0.
+ *   tol in (0, 1); max_iter >= 1 CGLS iterations per pole.
+ *   NEF_out [3] (N, E, F), density_out, dFdH_out [nnzb][bd][bd]: NULL skips;
+ *   host or device memory.  iterations_out [n_poles] (NULL skips): CGLS
+ *   iterations per pole, in the caller's pole order.
+ * After the call rfo_hf_forces uses this gradient (if requested), and
+ * rfo_density_forces this density (if requested without the gradient).
+ * Requires FP64 precision and no overlap (RFO_E_UNSUPPORTED otherwise).
+ * Errors: RFO_E_STATE before H and probes; RFO_E_INVALID for bad arguments;
+ * RFO_E_NUMERIC if CGLS breaks down or does not converge within max_iter. */
+int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double *poles,
+                          const double *res_f, const double *res_g, const double *poly,
+                          double tol, int64_t max_iter, double *NEF_out, double *density_out,
+                          double *dFdH_out, int64_t *iterations_out);
+
+/* CGLS iterations and solves (one per pole) since the context was created. */
+int rfo_rational_stats(const rfo_ctx *ctx, int64_t *iterations, int64_t *solves);
+
 /* Conjugate-gradient iterations and solves since the context was created. */
 int rfo_cg_stats(const rfo_ctx *ctx, int64_t *iterations, int64_t *solves);
 

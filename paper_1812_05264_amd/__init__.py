@@ -4,9 +4,9 @@ The compute path is the HIP library librfo.so (include/rfo.h); this package hold
 its ctypes binding and a torch.autograd.Function around the free-energy gradient.
 """
 
-from ._rfo import Engine, RfoError, library_path, load, PRECISIONS  # noqa: F401
+from ._rfo import Engine, RfoError, library_path, load, PRECISIONS, rational_fit  # noqa: F401
 from .scan import find_mu  # noqa: F401
 from .colored import colored_probes, welsh_powell  # noqa: F401
 
 __all__ = ["Engine", "RfoError", "library_path", "load", "PRECISIONS", "find_mu",
-           "colored_probes", "welsh_powell"]
+           "colored_probes", "welsh_powell", "rational_fit"]

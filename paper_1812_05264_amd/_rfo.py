@@ -61,10 +61,14 @@ def load():
     lib.rfo_density_forces.argtypes = [vp, vp, vp, vp]
     lib.rfo_cg_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.rfo_step_timing.argtypes = [vp, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    lib.rfo_rational_fit.argtypes = [i32, dbl, dbl, dbl, dbl, vp, vp, vp, vp]
+    lib.rfo_rational_estimate.argtypes = [vp, dbl, i64, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
+    lib.rfo_rational_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     for f in ("rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
               "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing",
               "rfo_step_timing", "rfo_set_moment_doubling", "rfo_traces_at", "rfo_set_overlap",
-              "rfo_get_density_q", "rfo_density_forces", "rfo_cg_stats"):
+              "rfo_get_density_q", "rfo_density_forces", "rfo_cg_stats", "rfo_rational_fit",
+              "rfo_rational_estimate", "rfo_rational_stats"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -87,6 +91,27 @@ def _host(a, dtype):
     if isinstance(a, torch.Tensor):
         a = a.detach().cpu().numpy()
     return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _complex_pairs(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
+
+
+def rational_fit(n_nodes, T, mu, e_min, e_max):
+    """Pole fit of f and g (rfo_rational_fit, host only): dict(poles, res_f, res_g
+    (complex arrays of 2 n_nodes), f0, g0, g1)."""
+    lib = load()
+    m = 2 * int(n_nodes)
+    z, wf, wg = (np.empty((m, 2)) for _ in range(3))
+    poly = np.empty(3)
+    rc = lib.rfo_rational_fit(int(n_nodes), float(T), float(mu), float(e_min), float(e_max),
+                              _ptr(z), _ptr(wf), _ptr(wg), _ptr(poly))
+    if rc != RFO_OK:
+        raise RfoError(rc, "rfo_rational_fit rejected its arguments")
+    cx = lambda a: a[:, 0] + 1j * a[:, 1]
+    return {"poles": cx(z), "res_f": cx(wf), "res_g": cx(wg), "f0": float(poly[0]),
+            "g0": float(poly[1]), "g1": float(poly[2])}
 
 
 class Engine:
@@ -224,6 +249,33 @@ class Engine:
         out = np.empty((self.n_block_rows, 3))
         self._check(self._lib.rfo_density_forces(self._ctx, _ptr(dH), _ptr(dS), _ptr(out)))
         return out
+
+    # -- rfo_rational_estimate ------------------------------------------------------
+    def rational(self, mu, fit, tol=1e-10, max_iter=100000, density=False, gradient=False,
+                 density_out=None, dFdH_out=None):
+        """Rational estimate with the fit dict of rational_fit (or any poles/residues of
+        the same form).  Returns dict(N, E, F, density, dFdH, iterations)."""
+        z, wf, wg = (_complex_pairs(fit[k]) for k in ("poles", "res_f", "res_g"))
+        poly = np.array([fit["f0"], fit["g0"], fit["g1"]], dtype=np.float64)
+        npol = z.shape[0]
+        nef = np.empty(3)
+        its = np.empty(npol, dtype=np.int64)
+        dens = density_out
+        if density and dens is None:
+            dens = np.empty((self.nnzb, self.block_dim, self.block_dim))
+        g = dFdH_out
+        if gradient and g is None:
+            g = np.empty((self.nnzb, self.block_dim, self.block_dim))
+        self._check(self._lib.rfo_rational_estimate(
+            self._ctx, float(mu), npol, _ptr(z), _ptr(wf), _ptr(wg), _ptr(poly), float(tol),
+            int(max_iter), _ptr(nef), _ptr(dens), _ptr(g), _ptr(its)))
+        return {"N": float(nef[0]), "E": float(nef[1]), "F": float(nef[2]), "density": dens,
+                "dFdH": g, "iterations": its}
+
+    def rational_stats(self):
+        it, so = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self._lib.rfo_rational_stats(self._ctx, ctypes.byref(it), ctypes.byref(so)))
+        return it.value, so.value
 
     def cg_stats(self):
         it, so = ctypes.c_int64(), ctypes.c_int64()

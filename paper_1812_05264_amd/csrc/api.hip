@@ -58,6 +58,11 @@ struct rfo_ctx {
   double *cg_res_h = nullptr;
   int64_t cg_iters = 0, cg_solves = 0;
   int64_t mom_p = 0;     // moments of the last call still valid on the device (0 = none)
+  // rational expansion: complex CGLS planes, column partials, scalars, r . x per pole
+  DevBuf rat, rat_part, rat_sc, rat_rho, rat_coef;
+  std::vector<double> rat_coef_h;
+  double *rat_res_h = nullptr;
+  int64_t cgls_iters = 0, cgls_solves = 0;
 
   // instrumentation
   bool timing = false;
@@ -69,7 +74,7 @@ struct rfo_ctx {
   ~rfo_ctx() {
     hipSetDevice(device);
     DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch, &nz_up, &nz_low,
-                     &s64, &cg_part, &cg_sc, &GQ,
+                     &s64, &cg_part, &cg_sc, &GQ, &rat, &rat_part, &rat_sc, &rat_rho, &rat_coef,
                      &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
                      &costab, &small, &flags, &G, &dHdR, &forces};
     for (DevBuf *b : all)
@@ -77,6 +82,7 @@ struct rfo_ctx {
     for (hipEvent_t e : events) hipEventDestroy(e);
     if (flags_h) hipHostFree(flags_h);
     if (cg_res_h) hipHostFree(cg_res_h);
+    if (rat_res_h) hipHostFree(rat_res_h);
   }
 };
 
@@ -494,6 +500,99 @@ int copy_moments_out(rfo_ctx *ctx, int64_t p, double *moments_out) {
     for (int64_t k = 0; k < p; ++k) outv[(size_t)c * p + k] = tmp[(size_t)k * ctx->sp + c];
   HIPCHK(hipMemcpy(moments_out, outv.data(), outv.size() * sizeof(double), hipMemcpyDefault));
   return RFO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Rational expansion with S = I (Rational approximation, Eq. rational_PQ; the
+// rational free-energy derivative, Eq. rational_derivative with dS = 0).  The
+// solves run on the mapped H_hat already on the device:
+//   H - z = c (H_hat - z_hat),  c = (e_max - e_min)/2,  z_hat = (z - d)/c,
+//   d = (e_max + e_min)/2,  so (H - z)^{-1} y = x / c  with  (H_hat - z_hat) x = y.
+// ---------------------------------------------------------------------------
+struct CxWork {
+  double *x, *r, *p, *q, *s;  // complex: two planes each
+  double *acc;                // real plane: P r accumulator
+  double *part, *part2;       // column partials
+  double *sc;                 // CGLS scalars [7][sp] + resmax
+  int nparts;                 // rows of part / part2
+  int ppl;                    // probes per lane of the complex product
+  rfo::CspArgs ca;            // complex product arguments (x, out, z, part set per launch)
+};
+
+int cspmm(rfo_ctx *ctx, CxWork &w, const double *x, double *out, double zr, double zi,
+          double *part) {
+  w.ca.x = x;
+  w.ca.out = out;
+  w.ca.zr = zr;
+  w.ca.zi = zi;
+  w.ca.part = part;
+  HIPCHK(rfo::launch_cspmm(ctx->bd, w.ppl, w.ca, ctx->stream));
+  return RFO_OK;
+}
+
+// CGLS for (H_hat - z) x = y on every probe column, from the current x (first:
+// x = 0), until |y - (H_hat - z) x| <= tol |y| for every column (checked on the
+// host every fourth iteration; later iterations only shrink the residuals).
+int cgls_solve(rfo_ctx *ctx, CxWork &w, double zr, double zi, double tol, int64_t max_iter,
+               bool first, int64_t *iters) {
+  const int64_t n = ctx->n;
+  const int sp = ctx->sp;
+  const int G = rfo::cg_nparts(n), grid = w.ca.grid;
+  const uint64_t *sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
+  const double *rden = ctx->signs ? nullptr : P<double>(ctx->rden);
+  double *sc = w.sc;
+  double *yy = sc, *qq = sc + 2 * sp, *ssn = sc + 3 * sp, *rr = sc + 4 * sp, *al = sc + 5 * sp,
+         *be = sc + 6 * sp, *res_d = sc + 7 * sp;
+  const double tol2 = tol * tol;
+  auto converged = [&](bool &done) -> int {
+    HIPCHK(hipMemcpyAsync(ctx->rat_res_h, res_d, sizeof(double), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double res = *ctx->rat_res_h;
+    if (!std::isfinite(res))
+      return fail(ctx, RFO_E_NUMERIC, "CGLS produced a non-finite residual (shift %g%+gi)", zr, zi);
+    done = res <= tol2;
+    return RFO_OK;
+  };
+  if (!first) TRY(cspmm(ctx, w, w.x, w.q, zr, zi, nullptr));
+  HIPCHK(rfo::launch_cx_resid(sgn, rden, first ? nullptr : w.q, w.r, n, sp, w.part, w.part2,
+                              ctx->stream));
+  HIPCHK(rfo::launch_colreduce(w.part, G, sp, rr, ctx->stream));
+  HIPCHK(rfo::launch_colreduce(w.part2, G, sp, yy, ctx->stream));
+  // s = A^H r (A^H = H_hat - conj(z)), p = s
+  TRY(cspmm(ctx, w, w.r, w.s, zr, -zi, w.part));
+  HIPCHK(rfo::launch_colreduce(w.part, grid, sp, ssn, ctx->stream));
+  HIPCHK(rfo::launch_cgls_scalars(sc, sp, 0, res_d, ctx->stream));
+  HIPCHK(hipMemcpyAsync(w.p, w.s, (size_t)2 * n * sp * sizeof(double), hipMemcpyDeviceToDevice,
+                        ctx->stream));
+  bool done = false;
+  TRY(converged(done));
+  if (done) {
+    *iters = 0;
+    ++ctx->cgls_solves;
+    return RFO_OK;
+  }
+  for (int64_t it = 1; it <= max_iter; ++it) {
+    TRY(cspmm(ctx, w, w.p, w.q, zr, zi, w.part));  // q = A p
+    HIPCHK(rfo::launch_colreduce(w.part, grid, sp, qq, ctx->stream));
+    HIPCHK(rfo::launch_cgls_scalars(sc, sp, 1, res_d, ctx->stream));
+    HIPCHK(rfo::launch_cx_update(w.x, w.r, w.p, w.q, al, n, sp, w.part, ctx->stream));
+    HIPCHK(rfo::launch_colreduce(w.part, G, sp, rr, ctx->stream));
+    TRY(cspmm(ctx, w, w.r, w.s, zr, -zi, w.part));  // s = A^H r
+    HIPCHK(rfo::launch_colreduce(w.part, grid, sp, ssn, ctx->stream));
+    HIPCHK(rfo::launch_cgls_scalars(sc, sp, 2, res_d, ctx->stream));
+    HIPCHK(rfo::launch_cx_dir(w.s, w.p, be, n, sp, ctx->stream));
+    ++ctx->cgls_iters;
+    if (it % 4 != 0 && it != max_iter) continue;
+    TRY(converged(done));
+    if (done) {
+      *iters = it;
+      ++ctx->cgls_solves;
+      return RFO_OK;
+    }
+  }
+  return fail(ctx, RFO_E_NUMERIC, "CGLS did not reach %g in %lld iterations (shift %g%+gi)", tol,
+              (long long)max_iter, zr, zi);
 }
 
 }  // namespace
@@ -1253,6 +1352,223 @@ int rfo_density_forces(rfo_ctx *ctx, const double *dHdR, const double *dSdR, dou
   }
   TRY(copy_out(ctx, forces_out, ctx->forces.p, (size_t)ctx->nb * 3 * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double *poles,
+                          const double *res_f, const double *res_g, const double *poly, double tol,
+                          int64_t max_iter, double *NEF_out, double *density_out,
+                          double *dFdH_out, int64_t *iterations_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "no Hamiltonian: call rfo_set_hamiltonian first");
+  if (!ctx->has_r) return fail(ctx, RFO_E_STATE, "no probes: call rfo_set_probes first");
+  if (ctx->prec != RFO_FP64)
+    return fail(ctx, RFO_E_UNSUPPORTED, "the rational expansion runs in FP64 only");
+  if (ctx->has_s)
+    return fail(ctx, RFO_E_UNSUPPORTED, "the rational expansion supports S = I only");
+  if (n_poles < 1 || n_poles > 4096) return fail(ctx, RFO_E_INVALID, "n_poles must be in [1, 4096]");
+  if (!poles || !res_f || !res_g || !poly) return fail(ctx, RFO_E_INVALID, "NULL fit argument");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(ctx, RFO_E_INVALID, "tol must be in (0, 1)");
+  if (max_iter < 1 || max_iter > (1 << 24))
+    return fail(ctx, RFO_E_INVALID, "max_iter must be in [1, 2^24]");
+  if (!std::isfinite(mu)) return fail(ctx, RFO_E_INVALID, "mu must be finite");
+  for (int t = 0; t < 3; ++t)
+    if (!std::isfinite(poly[t])) return fail(ctx, RFO_E_INVALID, "non-finite polynomial part");
+  for (int64_t k = 0; k < 2 * n_poles; ++k)
+    if (!std::isfinite(poles[k]) || !std::isfinite(res_f[k]) || !std::isfinite(res_g[k]))
+      return fail(ctx, RFO_E_INVALID, "non-finite pole or residue");
+  for (int64_t k = 0; k < n_poles; ++k)
+    if (!(poles[2 * k + 1] > 0.0))
+      return fail(ctx, RFO_E_INVALID, "pole %lld is not in the upper half plane", (long long)k);
+  HIPCHK(hipSetDevice(ctx->device));
+  const int64_t n = ctx->n;
+  const int sp = ctx->sp;
+  const int64_t plane = n * sp;
+  const bool dens = density_out != nullptr, grad = dFdH_out != nullptr;
+  const double c = 0.5 * (ctx->e_max - ctx->e_min), d = 0.5 * (ctx->e_max + ctx->e_min);
+
+  // launch decomposition of the complex product: the step kernel's row groups
+  const Plan pl = make_plan(ctx);
+  CxWork w;
+  w.ppl = ctx->bd == 1 && sp % 128 == 0 ? 2 : 1;
+  if (const char *env = getenv("RFO_CPPL")) w.ppl = atoi(env) == 2 && sp % 128 == 0 ? 2 : 1;
+  memset(&w.ca, 0, sizeof(w.ca));
+  w.ca.row_ptr = P<int64_t>(ctx->row_ptr);
+  w.ca.col = P<int32_t>(ctx->col);
+  w.ca.hval = P<double>(ctx->h64);
+  w.ca.nb = ctx->nb;
+  w.ca.plane = plane;
+  w.ca.sp = sp;
+  w.ca.rows_per_wg = pl.rows_per_wg;
+  w.ca.n_rg = pl.n_rg;
+  w.ca.n_pt = sp / (64 * w.ppl);
+  {
+    const int occ = std::max(1, rfo::cspmm_blocks_per_cu(ctx->bd, w.ppl));
+    int64_t grid = (int64_t)ctx->cus * std::min(occ, 4);
+    if (const char *env = getenv("RFO_CGRID")) grid = std::max<int64_t>(8, atoll(env));
+    const int64_t units = (int64_t)w.ca.n_pt * w.ca.n_rg;
+    grid = std::min(grid, (units + 7) / 8 * 8);
+    w.ca.grid = (int)std::max<int64_t>(8, grid / 8 * 8);
+  }
+  w.nparts = std::max(rfo::cg_nparts(n), w.ca.grid);
+  TRY(ensure(ctx, ctx->rat, (size_t)11 * plane * sizeof(double)));
+  TRY(ensure(ctx, ctx->rat_part, (size_t)2 * w.nparts * sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->rat_sc, ((size_t)7 * sp + 1) * sizeof(double)));
+  TRY(ensure(ctx, ctx->rat_rho, ((size_t)2 * n_poles + 2) * sp * sizeof(double)));
+  TRY(ensure(ctx, ctx->rat_coef, (size_t)6 * n_poles * sizeof(double)));
+  TRY(ensure(ctx, ctx->small, 64 * sizeof(double)));
+  if (!ctx->rat_res_h) HIPCHK(hipHostMalloc((void **)&ctx->rat_res_h, sizeof(double), 0));
+  double *base = P<double>(ctx->rat);
+  w.x = base;
+  w.r = base + 2 * plane;
+  w.p = base + 4 * plane;
+  w.q = base + 6 * plane;
+  w.s = base + 8 * plane;
+  w.acc = base + 10 * plane;
+  w.part = P<double>(ctx->rat_part);
+  w.part2 = w.part + (size_t)w.nparts * sp;
+  w.sc = P<double>(ctx->rat_sc);
+  double *rho = P<double>(ctx->rat_rho);
+  double *m01 = rho + (size_t)2 * n_poles * sp;
+  const uint64_t *sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
+  const double *rden = ctx->signs ? nullptr : P<double>(ctx->rden);
+
+  // trace coefficients of r . x_k per pole: N w_k / c, E w_k z_k / c, F tau_k / c
+  ctx->rat_coef_h.assign((size_t)6 * n_poles, 0.0);
+  double ew = 0.0;
+  for (int64_t k = 0; k < n_poles; ++k) {
+    const double zr = poles[2 * k], zi = poles[2 * k + 1];
+    const double wr = res_f[2 * k], wi = res_f[2 * k + 1];
+    const double tr = res_g[2 * k], ti = res_g[2 * k + 1];
+    double *cf = ctx->rat_coef_h.data();
+    cf[2 * k] = wr / c;
+    cf[2 * k + 1] = wi / c;
+    cf[2 * (n_poles + k)] = (wr * zr - wi * zi) / c;
+    cf[2 * (n_poles + k) + 1] = (wr * zi + wi * zr) / c;
+    cf[2 * (2 * n_poles + k)] = tr / c;
+    cf[2 * (2 * n_poles + k) + 1] = ti / c;
+    ew += 2.0 * wr;
+  }
+  HIPCHK(hipMemcpyAsync(ctx->rat_coef.p, ctx->rat_coef_h.data(), ctx->rat_coef_h.size() * sizeof(double),
+                        hipMemcpyHostToDevice, ctx->stream));
+
+  // r . r and r . H_hat r per column: x = R, q = H_hat R
+  HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 1.0, w.x, w.x + plane, ctx->stream));
+  TRY(cspmm(ctx, w, w.x, w.q, 0.0, 0.0, nullptr));
+  HIPCHK(rfo::launch_cx_pdot(sgn, rden, w.x, w.q, n, sp, nullptr, 0.0, 0.0, w.part, w.part2,
+                             ctx->stream));
+  HIPCHK(rfo::launch_colreduce(w.part, rfo::cg_nparts(n), sp, m01, ctx->stream));
+  HIPCHK(rfo::launch_colreduce(w.part2, rfo::cg_nparts(n), sp, m01 + sp, ctx->stream));
+
+  rfo::SddmmArgs sa;
+  memset(&sa, 0, sizeof(sa));
+  sa.brow = P<int64_t>(ctx->brow);
+  sa.col = P<int32_t>(ctx->col);
+  sa.nnzb = ctx->nnzb;
+  sa.bd = ctx->bd;
+  sa.sp = sp;
+  sa.sgn = sgn;
+  sa.rden = rden;
+  sa.w = P<double>(ctx->w);
+  sa.count = 1;
+  sa.scale = 1.0;
+  sa.rest = 1.0;
+  sa.ppl = sddmm_ppl(ctx);
+  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
+  ctx->has_grad = ctx->has_dens = ctx->has_q = false;
+  if (grad) {
+    // the linear part of g: dF/dH = g1 sum_c w_c r_c r_c^T on the pattern
+    TRY(ensure(ctx, ctx->G, gbytes));
+    sa.xbase = w.x;
+    sa.ybase = nullptr;
+    sa.first = poly[2];
+    sa.G = P<double>(ctx->G);
+    sa.accumulate = 0;
+    HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
+  }
+  if (dens) HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, poly[0], w.acc, nullptr, ctx->stream));
+  HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 0.0, w.x, w.x + plane, ctx->stream));  // x = 0
+
+  // poles far from mu first, each solve warm-started from the previous solution
+  std::vector<int64_t> order((size_t)n_poles);
+  for (int64_t k = 0; k < n_poles; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    const double da = std::hypot(poles[2 * a] - mu, poles[2 * a + 1]);
+    const double db = std::hypot(poles[2 * b] - mu, poles[2 * b + 1]);
+    return da > db;
+  });
+  std::vector<int64_t> iters((size_t)n_poles, 0);
+  for (size_t t = 0; t < order.size(); ++t) {
+    const int64_t k = order[t];
+    const double zr = (poles[2 * k] - d) / c, zi = poles[2 * k + 1] / c;
+    TRY(cgls_solve(ctx, w, zr, zi, tol, max_iter, t == 0, &iters[k]));
+    // rho_k = r . x_k, and P r += 2 Re[(w_k / c) x_k]
+    const double wr = 2.0 * res_f[2 * k] / c, wi = 2.0 * res_f[2 * k + 1] / c;
+    HIPCHK(rfo::launch_cx_pdot(sgn, rden, w.x, w.x + plane, n, sp, dens ? w.acc : nullptr, wr, wi,
+                               w.part, w.part2, ctx->stream));
+    HIPCHK(rfo::launch_colreduce(w.part, rfo::cg_nparts(n), sp, rho + (size_t)2 * k * sp, ctx->stream));
+    HIPCHK(rfo::launch_colreduce(w.part2, rfo::cg_nparts(n), sp, rho + (size_t)(2 * k + 1) * sp,
+                                 ctx->stream));
+    if (grad) {
+      // -2 Re[(tau_k / c^2) x_a x_b] = -2 Re t (xr xr - xi xi) + 2 Im t (xr xi + xi xr)
+      const double tr = res_g[2 * k] / (c * c), ti = res_g[2 * k + 1] / (c * c);
+      sa.accumulate = 1;
+      sa.sym = 0;
+      sa.xbase = w.x;
+      sa.ybase = w.x;
+      sa.first = -2.0 * tr;
+      HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
+      sa.xbase = w.x + plane;
+      sa.ybase = w.x + plane;
+      sa.first = 2.0 * tr;
+      HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
+      sa.sym = 1;
+      sa.xbase = w.x;
+      sa.ybase = w.x + plane;
+      sa.first = 2.0 * ti;
+      HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
+      sa.sym = 0;
+    }
+  }
+  rfo::RationalScalars ks;
+  ks.f0 = poly[0];
+  ks.ew = ew;
+  ks.g0 = poly[1];
+  ks.g1 = poly[2];
+  ks.h0 = d;
+  ks.h1 = c;
+  double *obs = P<double>(ctx->small);
+  HIPCHK(rfo::launch_rational_traces(rho, m01, P<double>(ctx->w), P<double>(ctx->rat_coef),
+                                     (int)n_poles, sp, ks, obs, ctx->stream));
+  if (dens) {
+    // with the gradient in G the density goes through the Q buffer
+    DevBuf &db = grad ? ctx->GQ : ctx->G;
+    TRY(ensure(ctx, db, gbytes));
+    sa.accumulate = 0;
+    sa.sym = 0;
+    sa.xbase = w.acc;
+    sa.ybase = nullptr;
+    sa.first = 1.0;
+    sa.G = P<double>(db);
+    HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
+    TRY(copy_out(ctx, density_out, db.p, gbytes));
+    ctx->has_dens = !grad;
+  }
+  if (grad) {
+    TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
+    ctx->has_grad = true;
+  }
+  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  if (iterations_out) std::copy(iters.begin(), iters.end(), iterations_out);
+  return RFO_OK;
+}
+
+int rfo_rational_stats(const rfo_ctx *ctx, int64_t *iterations, int64_t *solves) {
+  if (!ctx || !iterations || !solves) return RFO_E_INVALID;
+  *iterations = ctx->cgls_iters;
+  *solves = ctx->cgls_solves;
   return RFO_OK;
 }
 

@@ -166,6 +166,11 @@ int cg_parts(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(
 
 int cg_nparts(int64_t n) { return cg_parts(n); }
 
+hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, nparts, sp, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int64_t n, int sp,
                           double *part, double *sc, hipStream_t s) {
   const int G = cg_parts(n);

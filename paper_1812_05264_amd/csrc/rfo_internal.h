@@ -178,4 +178,61 @@ hipError_t launch_cg_alpha(const double *p, const double *q, int64_t n, int sp, 
 hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, int64_t n, int sp,
                             double *part, double *sc, double *resmax, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Rational expansion with S = I: CGLS for (H_hat - z) x = y per probe column on
+// complex vectors stored as two real [n][sp] planes (re, then im, `plane`
+// elements apart).  Column partials are [nparts][sp]; launch_colreduce sums
+// them in a fixed order.  CGLS scalars sc = [yy | gam | qq | ssn | rr | alpha |
+// beta] (sp each).
+// ---------------------------------------------------------------------------
+hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out, hipStream_t s);
+
+// out = (H_hat - z) x, with the column partials of |out_c|^2 when part != nullptr
+// ([grid][sp]); same unit decomposition as the Chebyshev step (the value and
+// column arrays carry kStepPad zero entries past nnzb).
+struct CspArgs {
+  const int64_t *row_ptr;
+  const int32_t *col;
+  const double *hval;      // H_hat blocks (FP64)
+  const double *x;         // complex input (two planes)
+  double *out;             // complex output (two planes), not aliasing x
+  double zr, zi;           // the shift z
+  double *part;            // [grid][sp] partials or nullptr
+  int64_t nb;              // block rows
+  int64_t plane;           // n * sp
+  int sp;
+  int rows_per_wg;
+  int n_rg, n_pt;          // n_pt probe tiles of 64 * ppl
+  int grid;                // multiple of 8
+};
+hipError_t launch_cspmm(int bd, int ppl, const CspArgs &a, hipStream_t s);
+int cspmm_blocks_per_cu(int bd, int ppl);
+// dre = scale * y (probes), dim = 0 when non-null
+hipError_t launch_cx_fill(const uint64_t *sgn, const double *rden, int64_t n, int sp, double scale,
+                          double *dre, double *dim, hipStream_t s);
+// r = y - q (q == nullptr: r = y); partials |r_c|^2 and |y_c|^2 ([cg_nparts(n)][sp] each)
+hipError_t launch_cx_resid(const uint64_t *sgn, const double *rden, const double *q, double *r,
+                           int64_t n, int sp, double *part_rr, double *part_yy, hipStream_t s);
+// x += alpha_c p, r -= alpha_c q; partials |r_c|^2
+hipError_t launch_cx_update(double *x, double *r, const double *p, const double *q,
+                            const double *alpha, int64_t n, int sp, double *part, hipStream_t s);
+// p = s + beta_c p
+hipError_t launch_cx_dir(const double *sv, double *p, const double *beta, int64_t n, int sp,
+                         hipStream_t s);
+// partials y_c . a_c, y_c . b_c; acc += wr a - wi b when acc != nullptr
+hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double *a, const double *b,
+                          int64_t n, int sp, double *acc, double wr, double wi, double *part_a,
+                          double *part_b, hipStream_t s);
+// mode 0: gam = ssn, *resmax;  1: alpha = gam / qq;  2: beta = ssn / gam, gam = ssn, *resmax
+hipError_t launch_cgls_scalars(double *sc, int sp, int mode, double *resmax, hipStream_t s);
+struct RationalScalars {
+  double f0, ew, g0, g1;   // constant of f, 2 Re sum_k w_k, constant and slope of g
+  double h0, h1;           // r^T H r = h1 r^T H_hat r + h0 r^T r
+};
+// N, E, F from rho [n_poles][2][sp] (r_c . x_kc), m01 [2][sp] (r.r, r.H_hat r),
+// weights and coef [3][n_poles] complex (N, E, F coefficients of rho).
+hipError_t launch_rational_traces(const double *rho, const double *m01, const double *w,
+                                  const double *coef, int n_poles, int sp,
+                                  const RationalScalars &k, double *out3, hipStream_t s);
+
 }  // namespace rfo

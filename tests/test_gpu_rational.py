@@ -1,0 +1,132 @@
+"""Rational (pole) expansion on the GPU (Rational approximation, Eq. rational_fit,
+Eq. rational_PQ; Eq. rational_derivative with S = I): CGLS on the complex-shifted
+systems against the oracle's sparse-LU solves of the same fit.
+
+Tolerance: CGLS stops at |r - (H_hat - z_hat) x| <= tol |r| per column, so the
+solution error is at most kappa tol with kappa = |H_hat - z_hat| |(H_hat - z_hat)^{-1}|
+<= 2 / min_k dist(z_hat_k, [-1, 1]).  The cases below keep kappa below 100;
+with tol = 1e-13 every output is within 1e-11 of the exact solves, under the
+1e-10 normwise bar of the other FP64 parity tests."""
+
+import numpy as np
+import pytest
+
+from oracle import forces as ofo
+from oracle import rational as ra
+from tests.gpu_common import TOL, banner, engine_or_skip, rel
+from workloads import cu_cluster, identity_probes, rademacher, random_graph, simple_cubic
+
+pytestmark = pytest.mark.gpu
+
+
+def fit_for(H, nodes, T, mu):
+    import paper_1812_05264_amd as pkg
+    return pkg.rational_fit(nodes, T, mu, H.e_min, H.e_max)
+
+
+def load(eng, H, R, weights=None):
+    eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, H.block_dim, H.e_min, H.e_max, "fp64")
+    eng.set_probes(R, weights)
+
+
+CASES = {
+    # name: (system, s, T, mu, nodes)
+    "cu55_s72": (lambda: cu_cluster(55, config_id=71), 72, 0.3, 0.2, 12),
+    "sc6_s200": (lambda: simple_cubic(6, disorder=0.6, config_id=72), 200, 0.2, 0.1, 10),
+    "graph300_s64": (lambda: random_graph(300, config_id=73), 64, 0.25, 0.0, 8),
+    "cu13_s1000": (lambda: cu_cluster(13, config_id=74), 1000, 0.4, -0.1, 6),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_rational_matches_oracle(name):
+    banner(f"rational parity {name}")
+    make, s, T, mu, nodes = CASES[name]
+    obj = make()
+    H = obj.bsr() if hasattr(obj, "bsr") else obj
+    R = rademacher(H.n, s, config_id=75)
+    fit = fit_for(H, nodes, T, mu)
+    eng = engine_or_skip()
+    load(eng, H, R)
+    g = eng.rational(mu, fit, tol=1e-13, max_iter=20000, density=True, gradient=True)
+    o = ra.estimate(H, R, fit, density=True, gradient=True)
+    for k in ("N", "E", "F"):
+        assert abs(g[k] - o[k]) <= TOL * max(1.0, abs(o[k])), (k, g[k], o[k])
+    assert rel(g["density"], o["density"]) < TOL
+    assert rel(g["dFdH"], o["dFdH"]) < TOL
+    assert g["iterations"].shape == (2 * nodes,) and np.all(g["iterations"] >= 0)
+    if hasattr(obj, "dH_dR"):
+        D = obj.dH_dR()
+        assert rel(eng.hf_forces(D), ofo.hf_forces(H, o["dFdH"], D)) < TOL
+
+
+def test_rational_identity_probes_give_traces_of_the_fit():
+    """Dense (non +-1) probes R = I with unit weights: N, E, F are the traces of the
+    fitted functions over the eigenvalues, and P's blocks those of V f_rat V^T."""
+    banner("rational identity probes sc3")
+    H = simple_cubic(3, disorder=0.4, config_id=76)
+    T, mu = 0.3, 0.05
+    fit = fit_for(H, 16, T, mu)
+    eng = engine_or_skip()
+    load(eng, H, identity_probes(H.n), np.ones(H.n))
+    g = eng.rational(mu, fit, tol=1e-13, density=True)
+    x = ra.exact(H.to_dense(), fit)
+    for k in ("N", "E", "F"):
+        assert abs(g[k] - x[k]) <= TOL * max(1.0, abs(x[k])), k
+    rows, cols = H.block_rows(), H.col_idx.astype(np.int64)
+    assert np.max(np.abs(g["density"][:, 0, 0] - x["P"][rows, cols])) < 1e-10
+
+
+def test_rational_independent_of_pole_order_and_repeatable():
+    """The fit's poles in reverse order (other warm starts) give the same
+    observables within the solver tolerance; a repeated call is bitwise equal."""
+    banner("rational order cu19")
+    H = cu_cluster(19, config_id=77).bsr()
+    R = rademacher(H.n, 64, config_id=77)
+    fit = fit_for(H, 8, 0.3, 0.0)
+    rev = {k: (v[::-1].copy() if isinstance(v, np.ndarray) else v) for k, v in fit.items()}
+    eng = engine_or_skip()
+    load(eng, H, R)
+    a = eng.rational(0.0, fit, tol=1e-13, gradient=True)
+    b = eng.rational(0.0, rev, tol=1e-13, gradient=True)
+    c = eng.rational(0.0, fit, tol=1e-13, gradient=True)
+    for k in ("N", "E", "F"):
+        assert abs(a[k] - b[k]) <= TOL * max(1.0, abs(a[k]))
+        assert a[k] == c[k]
+    assert rel(a["dFdH"], b["dFdH"]) < TOL
+    assert np.array_equal(a["dFdH"], c["dFdH"])
+    assert np.array_equal(a["iterations"], c["iterations"])
+    it, so = eng.rational_stats()
+    assert so == 3 * 16 and it >= int(np.sum(a["iterations"]))
+
+
+def test_rational_error_paths():
+    banner("rational errors")
+    import paper_1812_05264_amd as pkg
+    H = simple_cubic(3, disorder=0.3, config_id=78)
+    R = rademacher(H.n, 8, config_id=78)
+    fit = fit_for(H, 4, 0.3, 0.0)
+    eng = engine_or_skip()
+    with pytest.raises(pkg.RfoError) as ei:
+        eng.rational(0.0, fit)
+    assert ei.value.status == "RFO_E_STATE"
+    load(eng, H, R)
+    bad = dict(fit, poles=np.conj(fit["poles"]))
+    with pytest.raises(pkg.RfoError) as ei:
+        eng.rational(0.0, bad)
+    assert ei.value.status == "RFO_E_INVALID"
+    for tol in (0.0, 1.0, float("nan")):
+        with pytest.raises(pkg.RfoError) as ei:
+            eng.rational(0.0, fit, tol=tol)
+        assert ei.value.status == "RFO_E_INVALID"
+    with pytest.raises(pkg.RfoError) as ei:
+        eng.rational(0.0, fit, tol=1e-14, max_iter=1)
+    assert ei.value.status == "RFO_E_NUMERIC"
+    # the context stays usable after an error
+    ok = eng.rational(0.0, fit, tol=1e-12)
+    assert np.isfinite(ok["N"])
+    eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 1, H.e_min, H.e_max, "fp32")
+    eng.set_probes(R)
+    with pytest.raises(pkg.RfoError) as ei:
+        eng.rational(0.0, fit)
+    assert ei.value.status == "RFO_E_UNSUPPORTED"
