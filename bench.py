@@ -24,6 +24,9 @@ Also reported on the same line:
                 radius 6 A) in place of the 256 Rademacher probes
   overlap       the nonorthogonal basis (S^-1 by conjugate gradients in every step)
                 on the 4,000-atom cluster, 200 terms, moments and P, Q blocks
+  rational      rational (pole) expansion with CGLS against the Chebyshev expansion
+                at matched tolerance on the 4,000-atom cluster (kT = 0.03 eV), both
+                with density blocks, errors against a 1e-10 Chebyshev run
 """
 
 import argparse
@@ -206,6 +209,74 @@ def overlap_leg(args):
     return out
 
 
+def rational_leg(args):
+    """Rational against polynomial at matched tolerance eps (the cost comparison of
+    the paper's Fig. optimization_fig(b)): the 4,000-atom Cu-like cluster, 128
+    Rademacher probes, kT = 0.03 eV, mu = 0, density blocks on.  Chebyshev with
+    p = ceil(ln(1/eps) (e_max - e_min) / (6.4 T)) terms (the paper's polynomial
+    error model); rational with the fewest contour-fit nodes whose largest error
+    of f on [e_min, e_max] is <= eps and CGLS to relative residual eps.  Errors of
+    N per atom and of the density blocks are against a Chebyshev run to 1e-10 on
+    the same probes, so the probe noise cancels."""
+    import numpy as np
+    import torch
+    import paper_1812_05264_amd as pkg
+    from workloads import cu_cluster, rademacher
+    cl = cu_cluster(4000, config_id=2)
+    H = cl.bsr()
+    T, mu = 0.03, 0.0
+    R = rademacher(H.n, 128, config_id=2)
+    eng = pkg.Engine(0)
+    eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, "fp64")
+    eng.set_probes(R)
+    width = H.e_max - H.e_min
+    p_of = lambda eps: int(np.ceil(np.log(1.0 / eps) * width / (6.4 * T)))
+    ref = eng.fermi_moments(T, mu, p_of(1e-10), moments=False, density=True)
+    x = np.linspace(H.e_min, H.e_max, 20001)
+    f_exact = 1.0 - np.tanh((x - mu) / (2.0 * T))
+
+    def fit_for(eps):
+        for n in range(1, 129):
+            fit = pkg.rational_fit(n, T, mu, H.e_min, H.e_max)
+            r = fit["f0"] + 2.0 * np.real((1.0 / (x[:, None] - fit["poles"])) @ fit["res_f"])
+            if np.max(np.abs(r - f_exact)) <= eps:
+                return n, fit
+        raise RuntimeError("no fit within 128 nodes")
+
+    eng.rational(mu, pkg.rational_fit(1, T, mu, H.e_min, H.e_max), tol=1e-2, density=True)
+    rows = []
+    for eps in [float(e) for e in args.rat_eps.split(",") if e]:
+        p = p_of(eps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g_p = eng.fermi_moments(T, mu, p, moments=False, density=True)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t0
+        nodes, fit = fit_for(eps)
+        it0, so0 = eng.rational_stats()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g_r = eng.rational(mu, fit, tol=eps, max_iter=200000, density=True)
+        torch.cuda.synchronize()
+        t_r = time.perf_counter() - t0
+        it1, so1 = eng.rational_stats()
+        dref = np.linalg.norm(ref["density"])
+        rows.append({
+            "eps": eps, "poly_terms": p, "poly_s": round(t_p, 4),
+            "rat_nodes": nodes, "rat_poles": 2 * nodes, "rat_s": round(t_r, 4),
+            "cgls_iterations": int(it1 - it0), "cgls_iterations_max_pole": int(np.max(g_r["iterations"])),
+            "poly_dN_per_atom": abs(g_p["N"] - ref["N"]) / cl.n_atoms,
+            "rat_dN_per_atom": abs(g_r["N"] - ref["N"]) / cl.n_atoms,
+            "poly_density_rel_err": float(np.linalg.norm(g_p["density"] - ref["density"]) / dref),
+            "rat_density_rel_err": float(np.linalg.norm(g_r["density"] - ref["density"]) / dref),
+        })
+        print(f"[bench] rational cu4k eps={eps:g}: poly {p} terms {t_p:.3f} s, rational "
+              f"{2 * nodes} poles {t_r:.3f} s ({it1 - it0} CGLS iterations)", flush=True)
+    eng.close()
+    return {"workload": "cu4k: 4,000-atom Cu-like cluster, 128 Rademacher probes, kT=0.03 eV, "
+                        "mu=0, density blocks", "atoms": cl.n_atoms, "points": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -222,10 +293,14 @@ def main():
                     help="coloring radius (A) of a multi-color probe energy_force run (0 = skip)")
     ap.add_argument("--ov-terms", type=int, default=200,
                     help="terms of the overlap (nonorthogonal basis) leg (0 = skip)")
+    ap.add_argument("--rat-eps", default="1e-3",
+                    help="tolerances of the rational-vs-polynomial leg (empty = skip)")
     ap.add_argument("--ef-terms", type=int, default=0,
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
                     help="run only the energy_force leg (for profiling)")
+    ap.add_argument("--only-rational", action="store_true",
+                    help="run only the rational-vs-polynomial leg (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="time a 2 GiB device-to-device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -251,6 +326,9 @@ def main():
         return
     if args.only_energy_force:
         print(json.dumps({"energy_force": energy_force(args)}))
+        return
+    if args.only_rational:
+        print(json.dumps({"rational": rational_leg(args)}))
         return
 
     import numpy as np
@@ -335,6 +413,9 @@ def main():
     if args.ov_terms > 0:
         torch.cuda.empty_cache()
         line["overlap"] = overlap_leg(args)
+    if args.rat_eps:
+        torch.cuda.empty_cache()
+        line["rational"] = rational_leg(args)
     print(json.dumps(line), flush=True)
 
 

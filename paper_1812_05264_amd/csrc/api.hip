@@ -516,6 +516,7 @@ struct CxWork {
   double *sc;                 // CGLS scalars [7][sp] + resmax
   int nparts;                 // rows of part / part2
   int ppl;                    // probes per lane of the complex product
+  int u;                      // neighbours (1x1) or blocks (9x9) per chunk
   rfo::CspArgs ca;            // complex product arguments (x, out, z, part set per launch)
 };
 
@@ -526,7 +527,7 @@ int cspmm(rfo_ctx *ctx, CxWork &w, const double *x, double *out, double zr, doub
   w.ca.zr = zr;
   w.ca.zi = zi;
   w.ca.part = part;
-  HIPCHK(rfo::launch_cspmm(ctx->bd, w.ppl, w.ca, ctx->stream));
+  HIPCHK(rfo::launch_cspmm(ctx->bd, w.ppl, w.u, w.ca, ctx->stream));
   return RFO_OK;
 }
 
@@ -576,12 +577,12 @@ int cgls_solve(rfo_ctx *ctx, CxWork &w, double zr, double zi, double tol, int64_
     TRY(cspmm(ctx, w, w.p, w.q, zr, zi, w.part));  // q = A p
     HIPCHK(rfo::launch_colreduce(w.part, grid, sp, qq, ctx->stream));
     HIPCHK(rfo::launch_cgls_scalars(sc, sp, 1, res_d, ctx->stream));
-    HIPCHK(rfo::launch_cx_update(w.x, w.r, w.p, w.q, al, n, sp, w.part, ctx->stream));
+    HIPCHK(rfo::launch_cx_update(w.r, w.q, al, n, sp, w.part, ctx->stream));
     HIPCHK(rfo::launch_colreduce(w.part, G, sp, rr, ctx->stream));
     TRY(cspmm(ctx, w, w.r, w.s, zr, -zi, w.part));  // s = A^H r
     HIPCHK(rfo::launch_colreduce(w.part, grid, sp, ssn, ctx->stream));
     HIPCHK(rfo::launch_cgls_scalars(sc, sp, 2, res_d, ctx->stream));
-    HIPCHK(rfo::launch_cx_dir(w.s, w.p, be, n, sp, ctx->stream));
+    HIPCHK(rfo::launch_cx_dir(w.s, w.p, w.x, al, be, n, sp, ctx->stream));  // x += alpha p, new p
     ++ctx->cgls_iters;
     if (it % 4 != 0 && it != max_iter) continue;
     TRY(converged(done));
@@ -1391,8 +1392,15 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   // launch decomposition of the complex product: the step kernel's row groups
   const Plan pl = make_plan(ctx);
   CxWork w;
-  w.ppl = ctx->bd == 1 && sp % 128 == 0 ? 2 : 1;
+  // two probes per lane where the tiles allow: one tile of 128 probes reads the
+  // H_hat blocks once per product (measured faster for 1x1 and 9x9 blocks)
+  w.ppl = sp % 128 == 0 ? 2 : 1;
   if (const char *env = getenv("RFO_CPPL")) w.ppl = atoi(env) == 2 && sp % 128 == 0 ? 2 : 1;
+  w.u = ctx->bd == 1 ? 4 : 1;
+  if (const char *env = getenv("RFO_CU")) {
+    const int u = atoi(env);
+    if (ctx->bd == 1 ? (u == 4 || u == 8) : (u == 1 || u == 2)) w.u = u;
+  }
   memset(&w.ca, 0, sizeof(w.ca));
   w.ca.row_ptr = P<int64_t>(ctx->row_ptr);
   w.ca.col = P<int32_t>(ctx->col);
@@ -1404,7 +1412,7 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   w.ca.n_rg = pl.n_rg;
   w.ca.n_pt = sp / (64 * w.ppl);
   {
-    const int occ = std::max(1, rfo::cspmm_blocks_per_cu(ctx->bd, w.ppl));
+    const int occ = std::max(1, rfo::cspmm_blocks_per_cu(ctx->bd, w.ppl, w.u));
     int64_t grid = (int64_t)ctx->cus * std::min(occ, 4);
     if (const char *env = getenv("RFO_CGRID")) grid = std::max<int64_t>(8, atoll(env));
     const int64_t units = (int64_t)w.ca.n_pt * w.ca.n_rg;

@@ -65,14 +65,28 @@ __global__ __launch_bounds__(kWG) void k_coldot(const double *__restrict__ a,
   }
 }
 
-// out[c] = sum_b part[b][c], b in increasing order
-__global__ __launch_bounds__(kWG) void k_colreduce(const double *__restrict__ part, int nparts,
-                                                   int sp, double *__restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= sp) return;
+// out[c] = sum_b part[b][c].  A workgroup of kRW waves takes 64 columns; wave w
+// sums the rows b = w, w + kRW, ... in increasing order and the kRW wave sums
+// are then added in wave order, so the result is bitwise reproducible.
+constexpr int kRW = 16;
+
+__global__ __launch_bounds__(64 * kRW) void k_colreduce(const double *__restrict__ part, int nparts,
+                                                        int sp, double *__restrict__ out) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 64 + lane;
+  __shared__ double red[kRW][64];
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * sp + c];
-  out[c] = s;
+  if (c < sp) {
+#pragma unroll 8
+    for (int b = wave; b < nparts; b += kRW) s += part[(int64_t)b * sp + c];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && c < sp) {
+    double t = red[0][lane];
+    for (int w = 1; w < kRW; ++w) t += red[w][lane];
+    out[c] = t;
+  }
 }
 
 // t = 0, r = y, p = y, part = column partials of y . y
@@ -167,7 +181,7 @@ int cg_parts(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(
 int cg_nparts(int64_t n) { return cg_parts(n); }
 
 hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, nparts, sp, out);
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, nparts, sp, out);
   return hipGetLastError();
 }
 
@@ -175,7 +189,7 @@ hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int6
                           double *part, double *sc, hipStream_t s) {
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(kWG), 0, s, y, t, r, p, n, sp, part);
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, G, sp, sc);
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp, sc);
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 0, (double *)nullptr);
   return hipGetLastError();
 }
@@ -184,7 +198,7 @@ hipError_t launch_cg_alpha(const double *p, const double *q, int64_t n, int sp, 
                            double *sc, hipStream_t s) {
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_coldot, dim3(G), dim3(kWG), 0, s, p, q, n, sp, part);
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, G, sp,
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp,
                      sc + 2 * sp);
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 1, (double *)nullptr);
   return hipGetLastError();
@@ -194,7 +208,7 @@ hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, in
                             double *part, double *sc, double *resmax, hipStream_t s) {
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kWG), 0, s, t, r, p, q, sc + 4 * sp, n, sp, part);
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + kWG - 1) / kWG), dim3(kWG), 0, s, part, G, sp,
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp,
                      sc + 3 * sp);
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 2, resmax);
   int64_t blocks = (n * sp + kWG - 1) / kWG;

@@ -7,7 +7,7 @@
 // Chebyshev vectors, so the real H_hat multiplies both planes with the same
 // gathers and block values.  Column sums (norms, inner products with the
 // probes) are written as per-workgroup partials and reduced in a fixed order
-// (k_colreduce), so every scalar is bitwise reproducible.
+// (launch_colreduce), so every scalar is bitwise reproducible.
 #include "device_util.h"
 #include "rfo_internal.h"
 
@@ -41,7 +41,7 @@ __device__ __forceinline__ void flush_norm(double (&nrm)[PPL], double (*red)[64 
 // out = (H_hat - z) x on complex planes, with the column partials of |out_c|^2.
 // Same persistent XCD-banded schedule as the Chebyshev step (Sched).  1x1
 // blocks: U neighbours per chunk, entries through the scalar cache; 9x9
-// blocks: one block per chunk, its 81 entries staged in the wave's LDS slice.
+// blocks: U blocks per chunk, their entries staged in the wave's LDS slice.
 template <int BD, int PPL, int U>
 __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
   constexpr int BB = BD * BD;
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
   const double zr = a.zr, zi = a.zi;
   const bool nrm_on = a.part != nullptr;
   __shared__ double red[kWaves][64 * PPL];
-  __shared__ double hs[BD == 1 ? 1 : kWaves][BD == 1 ? 1 : BB];
+  __shared__ double hs[BD == 1 ? 1 : kWaves][BD == 1 ? 1 : U * BB];
   double *prow = nrm_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
   if (nrm_on && wave == 0)
     for (int t = 0; t < a.n_pt; ++t)
@@ -110,41 +110,53 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
         }
       } else {
         double *hw = hs[wave];
-        constexpr int NH = (BB + 63) / 64;
-        for (int64_t nz = beg; nz < end; ++nz) {
+        constexpr int CH = U * BB;
+        constexpr int NH = (CH + 63) / 64;
+        for (int64_t nz = beg; nz < end; nz += U) {
+          // U blocks per chunk; the value and column arrays carry kStepPad zero
+          // blocks past nnzb, and blocks past the row's end get no FMAs
           double hv[NH];
 #pragma unroll
           for (int k = 0; k < NH; ++k) {
             const int e = k * 64 + lane;
-            if (e < BB) hv[k] = a.hval[nz * BB + e];
+            if (e < CH) hv[k] = a.hval[nz * BB + e];
           }
-          const int64_t J = sld(a.col + nz);
-          VecN<double, PPL> vr[BD], vi[BD];
+          int64_t J[U];
 #pragma unroll
-          for (int j = 0; j < BD; ++j) {
-            vr[j] = ldv<double, PPL>(xr + (J * BD + j) * sp + c0);
-            vi[j] = ldv<double, PPL>(xi + (J * BD + j) * sp + c0);
-          }
+          for (int u = 0; u < U; ++u) J[u] = sld(a.col + nz + u);
+          VecN<double, PPL> vr[U][BD], vi[U][BD];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int j = 0; j < BD; ++j) {
+              vr[u][j] = ldv<double, PPL>(xr + (J[u] * BD + j) * sp + c0);
+              vi[u][j] = ldv<double, PPL>(xi + (J[u] * BD + j) * sp + c0);
+            }
           __builtin_amdgcn_wave_barrier();
 #pragma unroll
           for (int k = 0; k < NH; ++k) {
             const int e = k * 64 + lane;
-            if (e < BB) hw[e] = hv[k];
+            if (e < CH) hw[e] = hv[k];
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-          for (int i = 0; i < BD; ++i)
+          for (int u = 0; u < U; ++u) {
+            if (nz + u < end) {
 #pragma unroll
-            for (int j = 0; j < BD; ++j) {
-              const double h = hw[i * BD + j];
+              for (int i = 0; i < BD; ++i)
 #pragma unroll
-              for (int q = 0; q < PPL; ++q) {
-                sr[i][q] = fma(h, vr[j].v[q], sr[i][q]);
-                si[i][q] = fma(h, vi[j].v[q], si[i][q]);
-              }
+                for (int j = 0; j < BD; ++j) {
+                  const double h = hw[u * BB + i * BD + j];
+#pragma unroll
+                  for (int q = 0; q < PPL; ++q) {
+                    sr[i][q] = fma(h, vr[u][j].v[q], sr[i][q]);
+                    si[i][q] = fma(h, vi[u][j].v[q], si[i][q]);
+                  }
+                }
             }
+          }
         }
       }
 #pragma unroll
@@ -171,9 +183,16 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
 
 namespace {
 
-const void *select_cspmm(int bd, int ppl) {
-  if (bd == 1) return ppl == 2 ? (const void *)k_cspmm<1, 2, 4> : (const void *)k_cspmm<1, 1, 4>;
-  if (bd == 9) return ppl == 2 ? (const void *)k_cspmm<9, 2, 1> : (const void *)k_cspmm<9, 1, 1>;
+// u: neighbours per chunk (1x1: 4 or 8; 9x9: blocks per chunk, 1 or 2)
+const void *select_cspmm(int bd, int ppl, int u) {
+  if (bd == 1) {
+    if (u == 8) return ppl == 2 ? (const void *)k_cspmm<1, 2, 8> : (const void *)k_cspmm<1, 1, 8>;
+    return ppl == 2 ? (const void *)k_cspmm<1, 2, 4> : (const void *)k_cspmm<1, 1, 4>;
+  }
+  if (bd == 9) {
+    if (u == 2) return ppl == 2 ? (const void *)k_cspmm<9, 2, 2> : (const void *)k_cspmm<9, 1, 2>;
+    return ppl == 2 ? (const void *)k_cspmm<9, 2, 1> : (const void *)k_cspmm<9, 1, 1>;
+  }
   return nullptr;
 }
 
@@ -184,18 +203,47 @@ __device__ __forceinline__ void row_range(int64_t n, int64_t &lo, int64_t &hi) {
   hi = n * (b + 1) / G;
 }
 
+// Thread layout of the row-range kernels: with sp < kWG (and kWG a multiple of
+// sp) the kWG / sp row lanes of a column take every (kWG / sp)-th row and their
+// sums are combined in lane order (ColLanes::finish); otherwise one thread per
+// column (a loop over columns when sp > kWG).
+struct ColLanes {
+  int nl, lr, c0, cstep;
+  __device__ ColLanes(int sp) {
+    nl = (sp < kWG && kWG % sp == 0) ? kWG / sp : 1;
+    lr = nl > 1 ? (int)threadIdx.x / sp : 0;
+    c0 = nl > 1 ? (int)threadIdx.x % sp : (int)threadIdx.x;
+    cstep = nl > 1 ? sp : kWG;
+  }
+  // stores the column sum v of column c into out[c] (row lane 0 after combining)
+  __device__ void finish(double v, int c, int sp, double *red, double *out) const {
+    if (nl == 1) {
+      out[c] = v;
+      return;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    if (lr == 0) {
+      double t = red[c];
+      for (int l = 1; l < nl; ++l) t += red[l * sp + c];
+      out[c] = t;
+    }
+    __syncthreads();
+  }
+};
+
 }  // namespace
 
-int cspmm_blocks_per_cu(int bd, int ppl) {
-  const void *f = select_cspmm(bd, ppl);
+int cspmm_blocks_per_cu(int bd, int ppl, int u) {
+  const void *f = select_cspmm(bd, ppl, u);
   if (!f) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWG, 0) != hipSuccess) return 0;
   return nb;
 }
 
-hipError_t launch_cspmm(int bd, int ppl, const CspArgs &a, hipStream_t s) {
-  const void *f = select_cspmm(bd, ppl);
+hipError_t launch_cspmm(int bd, int ppl, int u, const CspArgs &a, hipStream_t s) {
+  const void *f = select_cspmm(bd, ppl, u);
   if (!f || a.sp % (64 * ppl) != 0 || a.grid % 8 != 0 || a.grid <= 0) return hipErrorInvalidValue;
   CspArgs args = a;
   void *kargs[] = {&args};
@@ -225,9 +273,11 @@ __global__ __launch_bounds__(kWG) void k_cx_resid(const uint64_t *sgn, const dou
                                                   double *__restrict__ part_yy) {
   int64_t lo, hi;
   row_range(n, lo, hi);
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+  const ColLanes cl(sp);
+  __shared__ double red[kWG];
+  for (int c = cl.c0; c < sp; c += cl.cstep) {
     double rr = 0.0, yy = 0.0;
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t i = lo + cl.lr; i < hi; i += cl.nl) {
       const int64_t e = i * sp + c;
       const double y = probe_value(sgn, rden, i, sp, c);
       const double a = q ? y - q[e] : y;
@@ -237,45 +287,51 @@ __global__ __launch_bounds__(kWG) void k_cx_resid(const uint64_t *sgn, const dou
       rr = fma(b, b, fma(a, a, rr));
       yy = fma(y, y, yy);
     }
-    part_rr[(int64_t)blockIdx.x * sp + c] = rr;
-    part_yy[(int64_t)blockIdx.x * sp + c] = yy;
+    cl.finish(rr, c, sp, red, part_rr + (int64_t)blockIdx.x * sp);
+    cl.finish(yy, c, sp, red, part_yy + (int64_t)blockIdx.x * sp);
   }
 }
 
-// x += alpha_c p, r -= alpha_c q (complex planes, real alpha); partials of |r_c|^2
-__global__ __launch_bounds__(kWG) void k_cx_update(double *__restrict__ x, double *__restrict__ r,
-                                                   const double *__restrict__ p,
+// r -= alpha_c q (complex planes, real alpha); partials of |r_c|^2
+__global__ __launch_bounds__(kWG) void k_cx_update(double *__restrict__ r,
                                                    const double *__restrict__ q,
                                                    const double *__restrict__ alpha, int64_t n,
                                                    int sp, int64_t plane,
                                                    double *__restrict__ part) {
   int64_t lo, hi;
   row_range(n, lo, hi);
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+  const ColLanes cl(sp);
+  __shared__ double red[kWG];
+  for (int c = cl.c0; c < sp; c += cl.cstep) {
     const double al = alpha[c];
     double rr = 0.0;
 #pragma unroll 4
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t i = lo + cl.lr; i < hi; i += cl.nl) {
       const int64_t e = i * sp + c;
-      x[e] = fma(al, p[e], x[e]);
-      x[plane + e] = fma(al, p[plane + e], x[plane + e]);
       const double a = fma(-al, q[e], r[e]);
       const double b = fma(-al, q[plane + e], r[plane + e]);
       r[e] = a;
       r[plane + e] = b;
       rr = fma(b, b, fma(a, a, rr));
     }
-    part[(int64_t)blockIdx.x * sp + c] = rr;
+    cl.finish(rr, c, sp, red, part + (int64_t)blockIdx.x * sp);
   }
 }
 
-// p = s + beta_c p (both planes)
+// x += alpha_c p, then p = s + beta_c p (both planes): the step of the solution
+// along the direction of this iteration, and the next direction
 __global__ __launch_bounds__(kWG) void k_cx_dir(const double *__restrict__ sv, double *__restrict__ p,
+                                                double *__restrict__ x,
+                                                const double *__restrict__ alpha,
                                                 const double *__restrict__ beta, int64_t n2,
                                                 int sp) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n2;
-       e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = fma(beta[e % sp], p[e], sv[e]);
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % sp);
+    const double pv = p[e];
+    x[e] = fma(alpha[c], pv, x[e]);
+    p[e] = fma(beta[c], pv, sv[e]);
+  }
 }
 
 // partials of y_c . a_c and y_c . b_c; with acc: acc += wr a - wi b (= Re[(wr + i wi)(a + i b)])
@@ -287,9 +343,11 @@ __global__ __launch_bounds__(kWG) void k_cx_pdot(const uint64_t *sgn, const doub
                                                  double *__restrict__ part_b) {
   int64_t lo, hi;
   row_range(n, lo, hi);
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+  const ColLanes cl(sp);
+  __shared__ double red[kWG];
+  for (int c = cl.c0; c < sp; c += cl.cstep) {
     double sa = 0.0, sb = 0.0;
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t i = lo + cl.lr; i < hi; i += cl.nl) {
       const int64_t e = i * sp + c;
       const double y = probe_value(sgn, rden, i, sp, c);
       const double a = av[e], b = bv[e];
@@ -297,8 +355,8 @@ __global__ __launch_bounds__(kWG) void k_cx_pdot(const uint64_t *sgn, const doub
       sb = fma(y, b, sb);
       if (acc) acc[e] = fma(-wi, b, fma(wr, a, acc[e]));
     }
-    part_a[(int64_t)blockIdx.x * sp + c] = sa;
-    part_b[(int64_t)blockIdx.x * sp + c] = sb;
+    cl.finish(sa, c, sp, red, part_a + (int64_t)blockIdx.x * sp);
+    cl.finish(sb, c, sp, red, part_b + (int64_t)blockIdx.x * sp);
   }
 }
 
@@ -397,16 +455,16 @@ hipError_t launch_cx_resid(const uint64_t *sgn, const double *rden, const double
   return hipGetLastError();
 }
 
-hipError_t launch_cx_update(double *x, double *r, const double *p, const double *q,
-                            const double *alpha, int64_t n, int sp, double *part, hipStream_t s) {
-  hipLaunchKernelGGL(k_cx_update, dim3(cg_nparts(n)), dim3(kWG), 0, s, x, r, p, q, alpha, n, sp,
-                     n * sp, part);
+hipError_t launch_cx_update(double *r, const double *q, const double *alpha, int64_t n, int sp,
+                            double *part, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_update, dim3(cg_nparts(n)), dim3(kWG), 0, s, r, q, alpha, n, sp, n * sp,
+                     part);
   return hipGetLastError();
 }
 
-hipError_t launch_cx_dir(const double *sv, double *p, const double *beta, int64_t n, int sp,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(k_cx_dir, dim3(ew_blocks(2 * n * sp)), dim3(kWG), 0, s, sv, p, beta,
+hipError_t launch_cx_dir(const double *sv, double *p, double *x, const double *alpha,
+                         const double *beta, int64_t n, int sp, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_dir, dim3(ew_blocks(2 * n * sp)), dim3(kWG), 0, s, sv, p, x, alpha, beta,
                      2 * n * sp, sp);
   return hipGetLastError();
 }

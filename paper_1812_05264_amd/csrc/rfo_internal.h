@@ -205,20 +205,21 @@ struct CspArgs {
   int n_rg, n_pt;          // n_pt probe tiles of 64 * ppl
   int grid;                // multiple of 8
 };
-hipError_t launch_cspmm(int bd, int ppl, const CspArgs &a, hipStream_t s);
-int cspmm_blocks_per_cu(int bd, int ppl);
+// u: neighbours per chunk (1x1: 4 or 8; 9x9: blocks per chunk, 1 or 2)
+hipError_t launch_cspmm(int bd, int ppl, int u, const CspArgs &a, hipStream_t s);
+int cspmm_blocks_per_cu(int bd, int ppl, int u);
 // dre = scale * y (probes), dim = 0 when non-null
 hipError_t launch_cx_fill(const uint64_t *sgn, const double *rden, int64_t n, int sp, double scale,
                           double *dre, double *dim, hipStream_t s);
 // r = y - q (q == nullptr: r = y); partials |r_c|^2 and |y_c|^2 ([cg_nparts(n)][sp] each)
 hipError_t launch_cx_resid(const uint64_t *sgn, const double *rden, const double *q, double *r,
                            int64_t n, int sp, double *part_rr, double *part_yy, hipStream_t s);
-// x += alpha_c p, r -= alpha_c q; partials |r_c|^2
-hipError_t launch_cx_update(double *x, double *r, const double *p, const double *q,
-                            const double *alpha, int64_t n, int sp, double *part, hipStream_t s);
-// p = s + beta_c p
-hipError_t launch_cx_dir(const double *sv, double *p, const double *beta, int64_t n, int sp,
-                         hipStream_t s);
+// r -= alpha_c q; partials |r_c|^2
+hipError_t launch_cx_update(double *r, const double *q, const double *alpha, int64_t n, int sp,
+                            double *part, hipStream_t s);
+// x += alpha_c p, then p = s + beta_c p
+hipError_t launch_cx_dir(const double *sv, double *p, double *x, const double *alpha,
+                         const double *beta, int64_t n, int sp, hipStream_t s);
 // partials y_c . a_c, y_c . b_c; acc += wr a - wi b when acc != nullptr
 hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double *a, const double *b,
                           int64_t n, int sp, double *acc, double wr, double wi, double *part_a,
