@@ -167,3 +167,39 @@ def test_cu16k_forces_match_finite_differences(cu16k_grad, group):
     worst, floor = _fd_atoms(d, atoms)
     print(f"cu16k {group}: worst |FD + force| {worst:.2e} eV/A (rounding floor ~{floor:.1e})")
     assert worst < max(1e-4, 20 * floor)
+
+
+def test_cu4k_rational_agrees_with_chebyshev():
+    """The rational-expansion benchmark workload (4,000-atom cluster, 128 probes,
+    kT = 0.03 eV, the launch configuration the bench times): with a 30-node fit and
+    CGLS to 1e-10, N, E, F and the density blocks agree with a Chebyshev run
+    accurate to 1e-10 on the same probes, so the probe noise cancels and what is
+    left is bounded by the fits.  For Rademacher probes with weights 1/s,
+    |sum_c w_c r_c^T h(H) r_c| <= n sup|h| on the spectrum, so each trace differs
+    by at most 9 sup|fit error| per atom (up to the solver and series errors).
+    Also sum_I tr D_II = N."""
+    banner("fullsize rational cu4k")
+    import paper_1812_05264_amd as pkg
+    from oracle import rational as ra
+    from workloads import cu_cluster
+    cl = cu_cluster(4000, config_id=2)
+    H = cl.bsr()
+    T, mu = 0.03, 0.0
+    R = rademacher(H.n, 128, config_id=2)
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    p = int(np.ceil(np.log(1e10) * (H.e_max - H.e_min) / (6.4 * T)))
+    c = eng.fermi_moments(T, mu, p, moments=False, density=True)
+    fit = pkg.rational_fit(30, T, mu, H.e_min, H.e_max)
+    x = np.linspace(H.e_min, H.e_max, 40001)
+    err = {"N": np.max(np.abs(ra.evaluate(fit, x, "f") - fm.fermi(x, T, mu))),
+           "E": np.max(np.abs(ra.evaluate(fit, x, "ef") - fm.energy_weight(x, T, mu))),
+           "F": np.max(np.abs(ra.evaluate(fit, x, "g") - fm.free_energy(x, T, mu)))}
+    r = eng.rational(mu, fit, tol=1e-10, max_iter=100000, density=True)
+    for k in ("N", "E", "F"):
+        bound = 2.0 * 9.0 * err[k] + 1e-8
+        assert abs(r[k] - c[k]) / cl.n_atoms < bound, (k, r[k], c[k], bound)
+    assert rel(r["density"], c["density"]) < 1e-6, rel(r["density"], c["density"])
+    diag = H.block_rows() == H.col_idx
+    assert abs(np.trace(r["density"][diag], axis1=1, axis2=2).sum() - r["N"]) < 1e-9 * abs(r["N"])
