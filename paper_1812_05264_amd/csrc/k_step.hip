@@ -323,6 +323,61 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
     const int c0 = pt * (64 * PPL) + lane * PPL;
     const int64_t r0 = rg * a.rows_per_wg;
     const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
+    // one scalar row of the output: shift, sources, moments, store, accumulator
+    auto finish_row = [&](int64_t I, int i, const VT(&si)[PPL]) {
+        const int64_t row = I * BD + i;
+        const int64_t off = row * sp + c0;
+        VecN<VT, PPL> pv, xs;
+        if (has_prev) pv = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        VecN<VT, PPL> sv[3];
+        if (SRC) {
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+            if (t < nsrc) sv[t] = ldv_nt<VT, PPL>(srcp[t] + off);
+        }
+        if (m >= 2 || DBL) xs = ldv<VT, PPL>(x + off);
+        double r[PPL];
+        if (need_r) {
+          if (a.sgn) {
+            const uint64_t w = a.sgn[row * nw + (c0 >> 6)];
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) r[q] = ((w >> ((c0 + q) & 63)) & 1ull) ? 1.0 : -1.0;
+          } else {
+            const VecN<double, PPL> rv = ldv<double, PPL>(a.rden + off);
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) r[q] = rv.v[q];
+          }
+        }
+        VecN<VT, PPL> o;
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          VT v = c1 * si[q];
+          if (has_prev) v = fma(c2, pv.v[q], v);
+          if (add_r) v = (VT)((double)v + beta * r[q]);
+          if (SRC) {
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+              if (t < nsrc) v = fma(srw[t], sv[t].v[q], v);
+          }
+          o.v[q] = v;
+          if (mom_on) {
+            if (DBL) {
+              mom[q] = fma((double)v, (double)v, mom[q]);
+              mom2[q] = fma((double)v, (double)xs.v[q], mom2[q]);
+            } else {
+              mom[q] = fma(r[q], (double)v, mom[q]);
+            }
+          }
+        }
+        if (NT) stv_nt<VT, PPL>(out + off, o);
+        else stv<VT, PPL>(out + off, o);
+        if (m > 0) {
+          VecN<VT, PPL> av = NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
+          av = add_terms<VT, PPL>(av, m, al, pv, xs, o);
+          if (NT) stv_nt<VT, PPL>(acc + off, av);
+          else stv<VT, PPL>(acc + off, av);
+        }
+    };
     for (int64_t I = r0 + wave; I < r1; I += kWaves) {
       const int64_t beg = sld(a.row_ptr + I), end = sld(a.row_ptr + I + 1);
       VT s[BD][PPL];
@@ -379,60 +434,7 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
         use_chunk(nz, hv, xv);
       }
 #pragma unroll
-      for (int i = 0; i < BD; ++i) {
-        const int64_t row = I * BD + i;
-        const int64_t off = row * sp + c0;
-        VecN<VT, PPL> pv, xs;
-        if (has_prev) pv = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
-        VecN<VT, PPL> sv[3];
-        if (SRC) {
-#pragma unroll
-          for (int t = 0; t < 3; ++t)
-            if (t < nsrc) sv[t] = ldv_nt<VT, PPL>(srcp[t] + off);
-        }
-        if (m >= 2 || DBL) xs = ldv<VT, PPL>(x + off);
-        double r[PPL];
-        if (need_r) {
-          if (a.sgn) {
-            const uint64_t w = a.sgn[row * nw + (c0 >> 6)];
-#pragma unroll
-            for (int q = 0; q < PPL; ++q) r[q] = ((w >> ((c0 + q) & 63)) & 1ull) ? 1.0 : -1.0;
-          } else {
-            const VecN<double, PPL> rv = ldv<double, PPL>(a.rden + off);
-#pragma unroll
-            for (int q = 0; q < PPL; ++q) r[q] = rv.v[q];
-          }
-        }
-        VecN<VT, PPL> o;
-#pragma unroll
-        for (int q = 0; q < PPL; ++q) {
-          VT v = c1 * s[i][q];
-          if (has_prev) v = fma(c2, pv.v[q], v);
-          if (add_r) v = (VT)((double)v + beta * r[q]);
-          if (SRC) {
-#pragma unroll
-            for (int t = 0; t < 3; ++t)
-              if (t < nsrc) v = fma(srw[t], sv[t].v[q], v);
-          }
-          o.v[q] = v;
-          if (mom_on) {
-            if (DBL) {
-              mom[q] = fma((double)v, (double)v, mom[q]);
-              mom2[q] = fma((double)v, (double)xs.v[q], mom2[q]);
-            } else {
-              mom[q] = fma(r[q], (double)v, mom[q]);
-            }
-          }
-        }
-        if (NT) stv_nt<VT, PPL>(out + off, o);
-        else stv<VT, PPL>(out + off, o);
-        if (m > 0) {
-          VecN<VT, PPL> av = NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
-          av = add_terms<VT, PPL>(av, m, al, pv, xs, o);
-          if (NT) stv_nt<VT, PPL>(acc + off, av);
-          else stv<VT, PPL>(acc + off, av);
-        }
-      }
+      for (int i = 0; i < BD; ++i) finish_row(I, i, s[i]);
     }
   }
   if (mom_on && cur_pt >= 0) {
