@@ -365,9 +365,10 @@ def main():
     value = total_bytes / wall / 1e9
     achieved = b_step / (step_ms * 1e-3) / 1e9
     # the step kernel is launched as two variants: MODE 1 on the steps that
-    # update the density accumulator, MODE 0 on the others
-    kname = ("k_step1<double, double, 2, 8, 1, true, MODE>" if args.precision == "fp64"
-             else "k_step1<float, float, 4, 8, 1, true, MODE>")
+    # update the density accumulator, MODE 0 on the others (7 neighbours per
+    # chunk: every row of the lattice has 7 entries)
+    kname = ("k_step1<double, double, 2, 7, 1, true, MODE>" if args.precision == "fp64"
+             else "k_step1<float, float, 4, 7, 1, true, MODE>")
     traffic = measured_traffic("sc64_" + args.precision)
     print(f"[bench] sc64 {args.precision}: {wall / args.steps * 1e3:.1f} ms per call, step kernel "
           f"{step_ms * 1e3:.1f} us ({n_steps} steps), {achieved:.0f} GB/s, N={last['N']:.6f}",

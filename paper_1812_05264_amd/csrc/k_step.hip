@@ -68,8 +68,9 @@ __device__ __forceinline__ void zero_partials(double *prow, int n_pt, int wave, 
 // for RPI rows at once, so each wave keeps RPI * U vector loads in flight; the
 // streamed rows of y_{k-1} and the probe signs are requested before the
 // gathers.  The column and value arrays carry kStepPad zero entries past nnzb,
-// so a chunk may read past the end of the last row; entries past a row's end
-// get zero weight.  NT selects non-temporal hints for the streamed arrays.
+// so a chunk may read indices past the end of the last row; slots past a row's
+// end load nothing and get zero weight (U = 7 fits a 7-point stencil row in one
+// chunk).  NT selects non-temporal hints for the streamed arrays.
 // ---------------------------------------------------------------------------
 template <typename VT, typename MT, int PPL, int U, int RPI, bool NT, int MODE>
 __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
@@ -166,14 +167,21 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
         for (int r = 0; r < RPI; ++r)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            // slots past the row's end re-read the row's own vector (a cache hit)
+            // slots past the row's end issue no load (the L2 request rate is the
+            // step's limit) and get zero weight
             const int64_t Jc = sld(a.col + beg[r] + u);
             J[r][u] = beg[r] + u < end[r] ? Jc : Ir[r];
           }
 #pragma unroll
         for (int r = 0; r < RPI; ++r)
 #pragma unroll
-          for (int u = 0; u < U; ++u) xv[r][u] = ldv<VT, PPL>(x + J[r][u] * sp + c0);
+          for (int u = 0; u < U; ++u) {
+            if (beg[r] + u < end[r]) xv[r][u] = ldv<VT, PPL>(x + J[r][u] * sp + c0);
+            else {
+#pragma unroll
+              for (int q = 0; q < PPL; ++q) xv[r][u].v[q] = (VT)0;
+            }
+          }
 #pragma unroll
         for (int r = 0; r < RPI; ++r)
 #pragma unroll
@@ -184,7 +192,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
             for (int q = 0; q < PPL; ++q) s[r][q] = fma(h, xv[r][u].v[q], s[r][q]);
             // y_k of the row itself for the accumulator: every row stores its
             // diagonal, so one of the gathered rows is it
-            if ((m >= 2 || DBL) && J[r][u] == Ir[r]) xs[r] = xv[r][u];
+            if ((m >= 2 || DBL) && nz < end[r] && J[r][u] == Ir[r]) xs[r] = xv[r][u];
           }
       }
 #pragma unroll
@@ -198,14 +206,20 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
             J[u] = nz0 + u < end[r] ? Jc : Ir[r];
           }
 #pragma unroll
-          for (int u = 0; u < U; ++u) xv[u] = ldv<VT, PPL>(x + J[u] * sp + c0);
+          for (int u = 0; u < U; ++u) {
+            if (nz0 + u < end[r]) xv[u] = ldv<VT, PPL>(x + J[u] * sp + c0);
+            else {
+#pragma unroll
+              for (int q = 0; q < PPL; ++q) xv[u].v[q] = (VT)0;
+            }
+          }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
             const int64_t nz = nz0 + u;
             const VT h = nz < end[r] ? (VT)sld(hval + nz) : (VT)0;
 #pragma unroll
             for (int q = 0; q < PPL; ++q) s[r][q] = fma(h, xv[u].v[q], s[r][q]);
-            if ((m >= 2 || DBL) && J[u] == Ir[r]) xs[r] = xv[u];
+            if ((m >= 2 || DBL) && nz < end[r] && J[u] == Ir[r]) xs[r] = xv[u];
           }
         }
       }
@@ -398,9 +412,13 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
 #pragma unroll
         for (int u = 0; u < U; ++u) J[u] = sld(a.col + nz + u);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+        for (int u = 0; u < U; ++u) {
+          // a chunk slot past the row's end gathers nothing (its FMAs are skipped)
+          if (u == 0 || nz + u < end) {
 #pragma unroll
-          for (int j = 0; j < BD; ++j) xv[u][j] = ldv<VT, PPL>(x + (J[u] * BD + j) * sp + c0);
+            for (int j = 0; j < BD; ++j) xv[u][j] = ldv<VT, PPL>(x + (J[u] * BD + j) * sp + c0);
+          }
+        }
       };
       // H_hat chunk -> LDS, then the FMAs with LDS broadcasts
       auto use_chunk = [&](int64_t nz, const MT(&hv)[NH], const VecN<VT, PPL>(&xv)[U][BD]) {
@@ -503,10 +521,13 @@ namespace {
 
 template <typename VT, typename MT, int PPL, int MODE>
 const void *step_fn(int bd, int rpi) {
-  // 1x1: rpi = rows per wave iteration; 9x9: rpi = blocks per gather chunk
-  if (bd == 1)
+  // 1x1: rpi = rows per wave iteration with 8 neighbours per chunk, or 7: one
+  // row per iteration with 7 neighbours per chunk; 9x9: rpi = blocks per chunk
+  if (bd == 1) {
+    if (rpi == 7) return (const void *)k_step1<VT, MT, PPL, 7, 1, true, MODE>;
     return rpi == 2 ? (const void *)k_step1<VT, MT, PPL, 8, 2, true, MODE>
                     : (const void *)k_step1<VT, MT, PPL, 8, 1, true, MODE>;
+  }
   return rpi == 2 ? (const void *)k_step9<VT, MT, PPL, 2, true, MODE>
                   : (const void *)k_step9<VT, MT, PPL, 1, true, MODE>;
 }
@@ -534,7 +555,7 @@ const void *step_fn_m(int bd, int ppl, int rpi, int mode) {
 
 // mode: 0 plain, 1 density accumulator, 2 doubling moments, 3 vector sources
 const void *select_step(int bd, int precision, int ppl, int rpi, int mode) {
-  if ((bd != 1 && bd != 9) || rpi < 1 || rpi > 2) return nullptr;
+  if ((bd != 1 && bd != 9) || rpi < 1 || (rpi > 2 && !(bd == 1 && rpi == 7))) return nullptr;
   return precision == 0 ? step_fn_m<double, double>(bd, ppl, rpi, mode)
                         : step_fn_m<float, float>(bd, ppl, rpi, mode);
 }

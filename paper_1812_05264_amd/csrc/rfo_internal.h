@@ -49,7 +49,8 @@ struct StepArgs {
   int sp;
   int rows_per_wg;
   int n_rg, n_pt;
-  int rpi;                 // rows per wave iteration (1x1 blocks: 1 or 2)
+  int rpi;                 // 1x1 blocks: rows per wave iteration (1 or 2, 8 neighbours per
+                           // chunk) or 7 (one row, 7 neighbours per chunk); 9x9: blocks per chunk
   int grid;                // workgroups (multiple of 8); part has [grid][sp]
 };
 
