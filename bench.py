@@ -24,6 +24,11 @@ Also reported on the same line:
                 radius 6 A) in place of the 256 Rademacher probes
   overlap       the nonorthogonal basis (S^-1 by conjugate gradients in every step)
                 on the 4,000-atom cluster, 200 terms, moments and P, Q blocks
+  cluster_steps Chebyshev step throughput on the Cu-like clusters: cu4k in FP64 (4,000
+                atoms, 4000 terms, 128 probes) and cu16k in BF16 MFMA, FP32 and FP64
+                (16,000 atoms, 8000 terms, 256 probes), moments only, with the HBM and
+                arithmetic fractions and the energy errors against FP64 per atom
+  copy          a 2 GiB device-to-device copy, timed, as the practical streaming rate
   rational      rational (pole) expansion with CGLS against the Chebyshev expansion
                 at matched tolerance on the 4,000-atom cluster (kT = 0.03 eV), both
                 with density blocks, errors against a 1e-10 Chebyshev run
@@ -209,6 +214,85 @@ def overlap_leg(args):
     return out
 
 
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+
+
+def cluster_steps(args):
+    """Step throughput on the Cu-like cluster configurations: cu4k FP64 and cu16k in
+    BF16 MFMA (the configuration's precision), FP32 and FP64, one moment-only
+    fermi_moments call each (doubled moments: p/2 steps).  Step time from HIP events
+    on the library stream; algorithmic bytes per step as for sc64 (H_hat blocks in
+    the step's matrix type, columns and row pointers once, three vector streams, probe
+    bits); useful flops 2 * 81 * nnzb * s per step against the dense peak of
+    the step's arithmetic (FP64, FP32 vector, BF16 MFMA); N, E, F differences per atom
+    against the FP64 run on the same probes."""
+    import torch
+    import paper_1812_05264_amd as pkg
+    from workloads.configs import CONFIGS, build_hamiltonian
+    from workloads import rademacher
+    out = {}
+    for name, precs in (("cu4k", ["fp64"]), ("cu16k", ["bf16", "fp32", "fp64"])):
+        cfg = CONFIGS[name]
+        H, cl = build_hamiltonian(cfg)
+        s = cfg.n_probes
+        R = rademacher(H.n, s, config_id=cfg.config_id)
+        rows = {}
+        for prec in precs:
+            eng = pkg.Engine(0)
+            eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, prec)
+            eng.set_probes(R)
+            eng.fermi_moments(cfg.T, cfg.mu, 16, moments=False)
+            torch.cuda.synchronize()
+            eng.set_timing(True)
+            t0 = time.perf_counter()
+            g = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=False)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms, n_steps = eng.step_timing()
+            eng.set_timing(False)
+            eng.close()
+            vt = 8 if prec == "fp64" else 4
+            mt = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+            b = step_bytes(H, s, vt, mt, density=False)
+            flops = 2.0 * 81 * H.nnzb * s
+            gbs = b / (ms * 1e-3) / 1e9
+            tfs = flops / (ms * 1e-3) / 1e12
+            rows[prec] = {"seconds": round(wall, 4), "steps": n_steps, "step_us": round(ms * 1e3, 2),
+                          "bytes_per_step": int(b), "GB_per_s": round(gbs, 1),
+                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "TFLOP_per_s": round(tfs, 2),
+                          "frac_compute": round(tfs / PEAK_TFLOPS[prec], 4),
+                          "N": g["N"], "E": g["E"], "F": g["F"]}
+            print(f"[bench] {name} {prec}: {wall:.3f} s, step {ms * 1e3:.1f} us, {gbs:.0f} GB/s, "
+                  f"{tfs:.1f} TFLOP/s", flush=True)
+        if "fp64" in rows:
+            for prec, r in rows.items():
+                if prec != "fp64":
+                    for k in ("N", "E", "F"):
+                        r[f"d{k}_per_atom_vs_fp64"] = abs(r[k] - rows["fp64"][k]) / cl.n_atoms
+        out[name] = {"atoms": cl.n_atoms, "orbitals": H.n, "nnzb": H.nnzb, "probes": s,
+                     "n_terms": cfg.n_terms, "T_eV": cfg.T, "mu_eV": cfg.mu, "runs": rows}
+    return out
+
+
+def copy_bandwidth():
+    """Read + write GB/s of a 2 GiB device-to-device copy (the practical streaming rate)."""
+    import torch
+    n = 256 * 1024 * 1024
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(10):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 10
+    del x, y
+    torch.cuda.empty_cache()
+    return 2 * n * 8 / dt / 1e9
+
+
 def rational_leg(args):
     """Rational against polynomial at matched tolerance eps (the cost comparison of
     the paper's Fig. optimization_fig(b)): the 4,000-atom Cu-like cluster, 128
@@ -293,6 +377,8 @@ def main():
                     help="coloring radius (A) of a multi-color probe energy_force run (0 = skip)")
     ap.add_argument("--ov-terms", type=int, default=200,
                     help="terms of the overlap (nonorthogonal basis) leg (0 = skip)")
+    ap.add_argument("--cluster-steps", type=int, default=1,
+                    help="step throughput legs on the Cu-like clusters (0 = skip)")
     ap.add_argument("--rat-eps", default="1e-3",
                     help="tolerances of the rational-vs-polynomial leg (empty = skip)")
     ap.add_argument("--ef-terms", type=int, default=0,
@@ -396,6 +482,10 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "mean_launch_us": round(step_ms * 1e3, 2)},
     }
+    # the same achieved rate against what a plain device copy moves on this GPU
+    cb = copy_bandwidth()
+    line["roofline"]["copy_GBps"] = round(cb, 1)
+    line["roofline"]["frac_of_copy"] = round(achieved / cb, 4)
 
     if args.cpu_steps > 0:
         n_sample = args.cpu_steps
@@ -414,6 +504,9 @@ def main():
     if args.ov_terms > 0:
         torch.cuda.empty_cache()
         line["overlap"] = overlap_leg(args)
+    if args.cluster_steps:
+        torch.cuda.empty_cache()
+        line["cluster_steps"] = cluster_steps(args)
     if args.rat_eps:
         torch.cuda.empty_cache()
         line["rational"] = rational_leg(args)
