@@ -1467,6 +1467,8 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   }
   HIPCHK(hipMemcpyAsync(ctx->rat_coef.p, ctx->rat_coef_h.data(), ctx->rat_coef_h.size() * sizeof(double),
                         hipMemcpyHostToDevice, ctx->stream));
+  // the host array is rewritten by the next call: let the copy finish here
+  HIPCHK(hipStreamSynchronize(ctx->stream));
 
   // r . r and r . H_hat r per column: x = R, q = H_hat R
   HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 1.0, w.x, w.x + plane, ctx->stream));
