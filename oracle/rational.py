@@ -1,4 +1,4 @@
-"""Rational (pole) expansion of the Fermi-Dirac and free-energy functions, S = I.
+"""Rational (pole) expansion of the Fermi-Dirac and free-energy functions.
 
 Follows the paper's Rational approximation subsection and the rational part of
 Analytical free-energy derivatives:
@@ -12,6 +12,10 @@ Analytical free-energy derivatives:
         P y = f0 y + 2 Re sum_k w_k g_k,
         Q y = f0 H y + 2 Re [ y sum_k w_k + sum_k w_k z_k g_k ],
     solved here exactly by a sparse LU factorization (library primitive);
+  * with an overlap S (Eq. rational_PQ as printed): (H - z_k S) g_k = y,
+        P y = f0 S^{-1} y + 2 Re sum_k w_k g_k,   Q y = S^{-1} H P y,
+    N = tr[P S], E = tr[P H], F = tr g(H S^{-1}) estimated on the probes as
+    (S r).(P r), (H r).(P r) and g0 r.r + g1 (H r).(S^{-1} r) + 2 Re sum_k tau_k (S r).g_k;
   * the rational free-energy primitive F(y) = g0 y.y + g1 y.H y
         + 2 Re sum_k tau_k y^T G(z_k) y and its derivative (Eq.
     rational_derivative with dS = 0): dF(y)/dH_ab = g1 y_a y_b
@@ -114,13 +118,14 @@ def evaluate(fit, x, which="f"):
     raise ValueError(which)
 
 
-def shifted_solves(H, R, poles):
-    """g_k = (H - z_k I)^{-1} R for every pole (complex [n, s] each), by sparse LU."""
+def shifted_solves(H, R, poles, S=None):
+    """g_k = (H - z_k S)^{-1} R (S = I when None) for every pole (complex [n, s] each),
+    by sparse LU."""
     H = sp.csc_matrix(H, dtype=np.complex128)
     n = H.shape[0]
-    I = sp.identity(n, dtype=np.complex128, format="csc")
+    M = sp.identity(n, dtype=np.complex128, format="csc") if S is None else sp.csc_matrix(S, dtype=np.complex128)
     Rc = np.asarray(R, dtype=np.complex128)
-    return [spla.splu((H - z * I).tocsc()).solve(Rc) for z in poles]
+    return [spla.splu((H - z * M).tocsc()).solve(Rc) for z in poles]
 
 
 def masked_outer_complex(bsr, X, Y, weights):
@@ -132,6 +137,31 @@ def masked_outer_complex(bsr, X, Y, weights):
     Xb = (np.asarray(X) * np.asarray(weights)[None, :]).reshape(-1, bd, s)
     Yb = np.asarray(Y).reshape(-1, bd, s)
     return np.einsum("zac,zbc->zab", Xb[rows], Yb[cols])
+
+
+def estimate_overlap(bsr, S_values, R, fit, weights=None, density=False):
+    """N, E, F with an overlap S on H's pattern (Eq. rational_PQ); optionally the P
+    and Q blocks M (.) sum_c w_c (P r_c) r_c^T and M (.) sum_c w_c (Q r_c) r_c^T."""
+    R = np.asarray(R, dtype=np.float64)
+    s = R.shape[1]
+    w = est.default_weights(s) if weights is None else np.asarray(weights, dtype=np.float64)
+    H = bsr.to_scipy().tocsr().astype(np.float64)
+    S = bsr.with_values(S_values).to_scipy().tocsr().astype(np.float64)
+    z, wf, wg = fit["poles"], fit["res_f"], fit["res_g"]
+    gs = shifted_solves(H, R, z, S)
+    lu = spla.splu(sp.csc_matrix(S))
+    SiR = lu.solve(R)
+    SR, HR = S @ R, H @ R
+    PR = fit["f0"] * SiR + 2.0 * np.real(sum(wk * gk for wk, gk in zip(wf, gs)))
+    FR = (fit["g0"] * np.einsum("ic,ic->c", R, R) + fit["g1"] * np.einsum("ic,ic->c", HR, SiR)
+          + 2.0 * np.real(sum(tk * np.einsum("ic,ic->c", SR, gk) for tk, gk in zip(wg, gs))))
+    out = {"N": float(w @ np.einsum("ic,ic->c", SR, PR)),
+           "E": float(w @ np.einsum("ic,ic->c", HR, PR)),
+           "F": float(w @ FR)}
+    if density:
+        out["density"] = est.masked_outer(bsr, PR, R, w)
+        out["density_Q"] = est.masked_outer(bsr, lu.solve(H @ PR), R, w)
+    return out
 
 
 def estimate(bsr, R, fit, weights=None, density=False, gradient=False):
@@ -162,11 +192,19 @@ def estimate(bsr, R, fit, weights=None, density=False, gradient=False):
     return out
 
 
-def exact(H_dense, fit):
-    """Traces of the rational approximants over the eigenvalues of a dense symmetric H,
-    and P = V diag(f_rat(eps)) V^T."""
+def exact(H_dense, fit, S_dense=None):
+    """Traces of the rational approximants over the (generalized, with S) eigenvalues
+    of a dense symmetric H, P = V diag(f_rat(eps)) V^T and Q = V diag(eps f_rat(eps)) V^T
+    (V^T S V = I)."""
+    import scipy.linalg as sl
     Hs = np.asarray(H_dense, dtype=np.float64)
-    eps, V = np.linalg.eigh(0.5 * (Hs + Hs.T))
+    Hs = 0.5 * (Hs + Hs.T)
+    if S_dense is None:
+        eps, V = np.linalg.eigh(Hs)
+    else:
+        Ss = np.asarray(S_dense, dtype=np.float64)
+        eps, V = sl.eigh(Hs, 0.5 * (Ss + Ss.T))
     f = evaluate(fit, eps, "f")
     return {"N": float(np.sum(f)), "E": float(np.sum(evaluate(fit, eps, "ef"))),
-            "F": float(np.sum(evaluate(fit, eps, "g"))), "P": (V * f) @ V.T}
+            "F": float(np.sum(evaluate(fit, eps, "g"))), "P": (V * f) @ V.T,
+            "Q": (V * (eps * f)) @ V.T}

@@ -131,3 +131,47 @@ def test_gradient_with_identity_probes_is_the_density_matrix():
     P = ex.observables(H.to_dense(), T, mu)["P"]
     rows, cols = H.block_rows(), H.col_idx.astype(np.int64)
     assert np.max(np.abs(o["dFdH"][:, 0, 0] - P[rows, cols])) < 1e-9
+
+
+def overlap_system(n_atoms, cid):
+    from workloads.overlap import overlap_values, pencil_interval
+    cl = cu_cluster(n_atoms, config_id=cid)
+    H = cl.bsr()
+    S = overlap_values(cl)
+    a, b = pencil_interval(H, S)
+    return H.__class__(H.row_ptr, H.col_idx, H.values, 9, a, b), S
+
+
+def test_overlap_identity_reduces_to_orthogonal_estimate():
+    H = cu_cluster(19, config_id=64).bsr()
+    I = np.zeros_like(H.values)
+    I[H.block_rows() == H.col_idx] = np.eye(9)
+    R = rademacher(H.n, 6, config_id=64)
+    fit = ra.contour_fit(16, 0.3, 0.1, H.e_min, H.e_max)
+    o = ra.estimate_overlap(H, I, R, fit, density=True)
+    e = ra.estimate(H, R, fit, density=True)
+    for k in ("N", "E", "F"):
+        assert abs(o[k] - e[k]) < 1e-12 * max(1.0, abs(e[k])), k
+    assert np.max(np.abs(o["density"] - e["density"])) < 1e-13
+
+
+def test_overlap_identity_probes_give_generalized_traces_and_P_Q():
+    """With R = I and an overlap: N, E, F are the fitted functions summed over the
+    generalized eigenvalues, P = V f_rat V^T and Q = V eps f_rat V^T (V^T S V = I),
+    and with an accurate fit the exact generalized observables."""
+    from oracle import overlap as ov
+    H, S = overlap_system(13, 65)
+    T, mu = 0.3, 0.2
+    fit = ra.contour_fit(40, T, mu, H.e_min, H.e_max)
+    o = ra.estimate_overlap(H, S, identity_probes(H.n), fit, weights=np.ones(H.n), density=True)
+    Sd = H.with_values(S).to_dense()
+    x = ra.exact(H.to_dense(), fit, Sd)
+    for k in ("N", "E", "F"):
+        assert abs(o[k] - x[k]) < 1e-10 * max(1.0, abs(x[k])), k
+    rows, cols = H.block_rows(), H.col_idx.astype(np.int64)
+    blk = lambda M: np.stack([M[9 * i:9 * i + 9, 9 * j:9 * j + 9] for i, j in zip(rows, cols)])
+    assert np.max(np.abs(o["density"] - blk(x["P"]))) < 1e-11
+    assert np.max(np.abs(o["density_Q"] - blk(x["Q"]))) < 1e-10
+    e = ov.exact(H.to_dense(), Sd, T, mu, H.e_min, H.e_max)
+    for k in ("N", "E", "F"):
+        assert abs(o[k] - e[k]) < 1e-8 * max(1.0, abs(e[k])), k
