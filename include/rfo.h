@@ -206,7 +206,7 @@ int rfo_density_forces(rfo_ctx *ctx, const double *dHdR, const double *dSdR,
 int rfo_rational_fit(int n_nodes, double T, double mu, double e_min, double e_max,
                      double *poles, double *res_f, double *res_g, double *poly);
 
-/* Rational estimate with S = I (paper: Rational approximation, Eq. rational_PQ;
+/* Rational estimate (paper: Rational approximation, Eq. rational_PQ;
  * rational free-energy primitive and its derivative, Eq. rational_derivative
  * with dS = 0).  For every probe column the library solves the shifted systems
  * (H - z_k) g_k = r_c by CGLS (conjugate gradients on the normal equations)
@@ -226,9 +226,17 @@ int rfo_rational_fit(int n_nodes, double T, double mu, double e_min, double e_ma
  *   NEF_out [3] (N, E, F), density_out, dFdH_out [nnzb][bd][bd]: NULL skips;
  *   host or device memory.  iterations_out [n_poles] (NULL skips): CGLS
  *   iterations per pole, in the caller's pole order.
+ * With an overlap S set (rfo_set_overlap) the systems are (H - z_k S) g_k = r_c
+ * (Eq. rational_PQ as printed) and
+ *   P r = f0 S^{-1} r + 2 Re sum_k w_k g_k,   Q r = S^{-1} H P r,
+ *   N = sum_c w_c (S r_c).(P r_c),  E = sum_c w_c (H r_c).(P r_c),
+ *   F = sum_c w_c [g0 r_c.r_c + g1 (H r_c).(S^{-1} r_c) + 2 Re sum_k tau_k (S r_c).g_k],
+ * with S^{-1} by conjugate gradients (the overlap's cg_tol); the density call
+ * then also forms the Q blocks (rfo_get_density_q), and dFdH_out must be NULL.
  * After the call rfo_hf_forces uses this gradient (if requested), and
  * rfo_density_forces this density (if requested without the gradient).
- * Requires FP64 precision and no overlap (RFO_E_UNSUPPORTED otherwise).
+ * Requires FP64 precision (RFO_E_UNSUPPORTED otherwise, and for the gradient
+ * with an overlap).
  * Errors: RFO_E_STATE before H and probes; RFO_E_INVALID for bad arguments;
  * RFO_E_NUMERIC if CGLS breaks down or does not converge within max_iter. */
 int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double *poles,

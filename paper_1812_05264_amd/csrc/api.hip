@@ -1373,8 +1373,8 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   if (!ctx->has_r) return fail(ctx, RFO_E_STATE, "no probes: call rfo_set_probes first");
   if (ctx->prec != RFO_FP64)
     return fail(ctx, RFO_E_UNSUPPORTED, "the rational expansion runs in FP64 only");
-  if (ctx->has_s)
-    return fail(ctx, RFO_E_UNSUPPORTED, "the rational expansion supports S = I only");
+  if (ctx->has_s && dFdH_out)
+    return fail(ctx, RFO_E_UNSUPPORTED, "the rational free-energy gradient supports S = I only");
   if (n_poles < 1 || n_poles > 4096) return fail(ctx, RFO_E_INVALID, "n_poles must be in [1, 4096]");
   if (!poles || !res_f || !res_g || !poly) return fail(ctx, RFO_E_INVALID, "NULL fit argument");
   if (!(tol > 0.0 && tol < 1.0)) return fail(ctx, RFO_E_INVALID, "tol must be in (0, 1)");
@@ -1402,6 +1402,8 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   // two probes per lane where the tiles allow: one tile of 128 probes reads the
   // H_hat blocks once per product (measured faster for 1x1 and 9x9 blocks)
   w.ppl = sp % 128 == 0 ? 2 : 1;
+  // with an overlap the 9x9 product keeps four row sums per probe: one probe per lane
+  if (ctx->has_s && ctx->bd == 9) w.ppl = 1;
   if (const char *env = getenv("RFO_CPPL")) w.ppl = atoi(env) == 2 && sp % 128 == 0 ? 2 : 1;
   w.u = ctx->bd == 1 ? 4 : 1;
   if (const char *env = getenv("RFO_CU")) {
@@ -1411,7 +1413,8 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   memset(&w.ca, 0, sizeof(w.ca));
   w.ca.row_ptr = P<int64_t>(ctx->row_ptr);
   w.ca.col = P<int32_t>(ctx->col);
-  w.ca.hval = P<double>(ctx->h64);
+  w.ca.hval = P<double>(ctx->h64);                            // H_hat (mapped with S when set)
+  w.ca.sval = ctx->has_s ? P<double>(ctx->s64) : nullptr;
   w.ca.nb = ctx->nb;
   w.ca.plane = plane;
   w.ca.sp = sp;
@@ -1419,7 +1422,7 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   w.ca.n_rg = pl.n_rg;
   w.ca.n_pt = sp / (64 * w.ppl);
   {
-    const int occ = std::max(1, rfo::cspmm_blocks_per_cu(ctx->bd, w.ppl, w.u));
+    const int occ = std::max(1, rfo::cspmm_blocks_per_cu(ctx->bd, w.ppl, w.u, ctx->has_s));
     int64_t grid = (int64_t)ctx->cus * std::min(occ, 4);
     if (const char *env = getenv("RFO_CGRID")) grid = std::max<int64_t>(8, atoll(env));
     const int64_t units = (int64_t)w.ca.n_pt * w.ca.n_rg;
@@ -1427,7 +1430,12 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
     w.ca.grid = (int)std::max<int64_t>(8, grid / 8 * 8);
   }
   w.nparts = std::max(rfo::cg_nparts(n), w.ca.grid);
-  TRY(ensure(ctx, ctx->rat, (size_t)11 * plane * sizeof(double)));
+  // planes: x, r, p, q, s (complex), the P r accumulator, and S r with an overlap
+  TRY(ensure(ctx, ctx->rat, (size_t)(ctx->has_s ? 12 : 11) * plane * sizeof(double)));
+  if (ctx->has_s) {
+    TRY(ensure(ctx, ctx->vec, 6 * pl.vec_elems * pl.vt_bytes));  // CG work slots
+    TRY(ensure_cg(ctx));
+  }
   TRY(ensure(ctx, ctx->rat_part, (size_t)2 * w.nparts * sp * sizeof(double)));
   TRY(ensure(ctx, ctx->rat_sc, ((size_t)7 * sp + 1) * sizeof(double)));
   TRY(ensure(ctx, ctx->rat_rho, ((size_t)2 * n_poles + 2) * sp * sizeof(double)));
@@ -1470,13 +1478,31 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   // the host array is rewritten by the next call: let the copy finish here
   HIPCHK(hipStreamSynchronize(ctx->stream));
 
-  // r . r and r . H_hat r per column: x = R, q = H_hat R
+  // x = R;  q = H R / c, the product with the shift -d/c (H = c H_hat + d S)
   HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 1.0, w.x, w.x + plane, ctx->stream));
-  TRY(cspmm(ctx, w, w.x, w.q, 0.0, 0.0, nullptr));
-  HIPCHK(rfo::launch_cx_pdot(sgn, rden, w.x, w.q, n, sp, nullptr, 0.0, 0.0, w.part, w.part2,
+  TRY(cspmm(ctx, w, w.x, w.q, -d / c, 0.0, nullptr));
+  // with an overlap: S r (kept for the whole call) and S^{-1} r (in p, by CG)
+  double *Sr = nullptr, *SiR = nullptr;
+  if (ctx->has_s) {
+    Sr = base + 11 * plane;
+    SiR = w.p;
+    const double *hv = w.ca.hval, *sv = w.ca.sval;
+    w.ca.hval = sv;  // the plain product with S
+    w.ca.sval = nullptr;
+    TRY(cspmm(ctx, w, w.x, w.s, 0.0, 0.0, nullptr));
+    w.ca.hval = hv;
+    w.ca.sval = sv;
+    HIPCHK(rfo::launch_cx_scale(w.s, Sr, plane, 1.0, ctx->stream));
+    TRY(cg_solve(ctx, pl, ctx->vec, w.x, SiR));
+  }
+  // m0 = r . r and h = (H r) . (S^{-1} r) per column
+  HIPCHK(rfo::launch_cx_pdot(sgn, rden, nullptr, w.x, w.x, n, sp, nullptr, 0.0, 0.0, w.part, w.part2,
                              ctx->stream));
   HIPCHK(rfo::launch_colreduce(w.part, rfo::cg_nparts(n), sp, m01, ctx->stream));
-  HIPCHK(rfo::launch_colreduce(w.part2, rfo::cg_nparts(n), sp, m01 + sp, ctx->stream));
+  HIPCHK(rfo::launch_cx_pdot(sgn, rden, SiR, w.q, w.q, n, sp, nullptr, 0.0, 0.0, w.part, w.part2,
+                             ctx->stream));
+  HIPCHK(rfo::launch_colreduce(w.part, rfo::cg_nparts(n), sp, m01 + sp, ctx->stream));
+  HIPCHK(rfo::launch_cx_scale(m01 + sp, m01 + sp, sp, c, ctx->stream));
 
   rfo::SddmmArgs sa;
   memset(&sa, 0, sizeof(sa));
@@ -1504,7 +1530,11 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
     sa.accumulate = 0;
     HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
   }
-  if (dens) HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, poly[0], w.acc, nullptr, ctx->stream));
+  // P r starts at f0 S^{-1} r
+  if (dens) {
+    if (SiR) HIPCHK(rfo::launch_cx_scale(SiR, w.acc, plane, poly[0], ctx->stream));
+    else HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, poly[0], w.acc, nullptr, ctx->stream));
+  }
   HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 0.0, w.x, w.x + plane, ctx->stream));  // x = 0
 
   // poles far from mu first, each solve warm-started from the previous solution
@@ -1520,9 +1550,9 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
     const int64_t k = order[t];
     const double zr = (poles[2 * k] - d) / c, zi = poles[2 * k + 1] / c;
     TRY(cgls_solve(ctx, w, zr, zi, tol, max_iter, t == 0, &iters[k]));
-    // rho_k = r . x_k, and P r += 2 Re[(w_k / c) x_k]
+    // rho_k = (S r) . x_k, and P r += 2 Re[(w_k / c) x_k]
     const double wr = 2.0 * res_f[2 * k] / c, wi = 2.0 * res_f[2 * k + 1] / c;
-    HIPCHK(rfo::launch_cx_pdot(sgn, rden, w.x, w.x + plane, n, sp, dens ? w.acc : nullptr, wr, wi,
+    HIPCHK(rfo::launch_cx_pdot(sgn, rden, Sr, w.x, w.x + plane, n, sp, dens ? w.acc : nullptr, wr, wi,
                                w.part, w.part2, ctx->stream));
     HIPCHK(rfo::launch_colreduce(w.part, rfo::cg_nparts(n), sp, rho + (size_t)2 * k * sp, ctx->stream));
     HIPCHK(rfo::launch_colreduce(w.part2, rfo::cg_nparts(n), sp, rho + (size_t)(2 * k + 1) * sp,
@@ -1553,8 +1583,6 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   ks.ew = ew;
   ks.g0 = poly[1];
   ks.g1 = poly[2];
-  ks.h0 = d;
-  ks.h1 = c;
   double *obs = P<double>(ctx->small);
   HIPCHK(rfo::launch_rational_traces(rho, m01, P<double>(ctx->w), P<double>(ctx->rat_coef),
                                      (int)n_poles, sp, ks, obs, ctx->stream));
@@ -1571,6 +1599,19 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
     HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
     TRY(copy_out(ctx, density_out, db.p, gbytes));
     ctx->has_dens = !grad;
+    if (ctx->has_s) {
+      // Q r = S^{-1} H P r: x = (P r, 0), q = H P r / c, then CG
+      HIPCHK(rfo::launch_cx_scale(w.acc, w.x, plane, 1.0, ctx->stream));
+      HIPCHK(hipMemsetAsync(w.x + plane, 0, (size_t)plane * sizeof(double), ctx->stream));
+      TRY(cspmm(ctx, w, w.x, w.q, -d / c, 0.0, nullptr));
+      HIPCHK(rfo::launch_cx_scale(w.q, w.r, plane, c, ctx->stream));
+      TRY(cg_solve(ctx, pl, ctx->vec, w.r, w.p));
+      TRY(ensure(ctx, ctx->GQ, gbytes));
+      sa.xbase = w.p;
+      sa.G = P<double>(ctx->GQ);
+      HIPCHK(rfo::launch_sddmm(0, sa, ctx->stream));
+      ctx->has_q = true;
+    }
   }
   if (grad) {
     TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));

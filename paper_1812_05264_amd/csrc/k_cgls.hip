@@ -38,13 +38,15 @@ __device__ __forceinline__ void flush_norm(double (&nrm)[PPL], double (*red)[64 
 
 }  // namespace
 
-// out = (H_hat - z) x on complex planes, with the column partials of |out_c|^2.
-// Same persistent XCD-banded schedule as the Chebyshev step (Sched).  1x1
-// blocks: U neighbours per chunk, entries through the scalar cache; 9x9
-// blocks: U blocks per chunk, their entries staged in the wave's LDS slice.
-template <int BD, int PPL, int U>
+// out = (H_hat - z) x on complex planes, with the column partials of |out_c|^2;
+// HS: out = H_hat x - z (S x) with the overlap S on the same pattern (H_hat then
+// maps H with S).  Same persistent XCD-banded schedule as the Chebyshev step
+// (Sched).  1x1 blocks: U neighbours per chunk, entries through the scalar cache;
+// 9x9 blocks: U blocks per chunk, their entries staged in the wave's LDS slice.
+template <int BD, int PPL, int U, bool HS>
 __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
   constexpr int BB = BD * BD;
+  constexpr int NM = HS ? 2 : 1;  // matrices applied to x: H_hat (and S)
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int sp = a.sp;
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
   const double zr = a.zr, zi = a.zi;
   const bool nrm_on = a.part != nullptr;
   __shared__ double red[kWaves][64 * PPL];
-  __shared__ double hs[BD == 1 ? 1 : kWaves][BD == 1 ? 1 : U * BB];
+  __shared__ double hs[BD == 1 ? 1 : kWaves][BD == 1 ? 1 : NM * U * BB];
   double *prow = nrm_on ? a.part + (int64_t)blockIdx.x * sp : nullptr;
   if (nrm_on && wave == 0)
     for (int t = 0; t < a.n_pt; ++t)
@@ -78,11 +80,16 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
     const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
     for (int64_t I = r0 + wave; I < r1; I += kWaves) {
       const int64_t beg = sld(a.row_ptr + I), end = sld(a.row_ptr + I + 1);
-      double sr[BD][PPL], si[BD][PPL];
+      double sr[BD][PPL], si[BD][PPL];        // H_hat x
+      double tr[HS ? BD : 1][PPL], ti[HS ? BD : 1][PPL];  // S x
 #pragma unroll
       for (int i = 0; i < BD; ++i)
 #pragma unroll
         for (int q = 0; q < PPL; ++q) sr[i][q] = si[i][q] = 0.0;
+#pragma unroll
+      for (int i = 0; i < (HS ? BD : 1); ++i)
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) tr[i][q] = ti[i][q] = 0.0;
       if constexpr (BD == 1) {
         for (int64_t nz0 = beg; nz0 < end; nz0 += U) {
           int64_t J[U];
@@ -106,12 +113,20 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
               sr[0][q] = fma(h, vr[u].v[q], sr[0][q]);
               si[0][q] = fma(h, vi[u].v[q], si[0][q]);
             }
+            if constexpr (HS) {
+              const double sv = nz0 + u < end ? sld(a.sval + nz0 + u) : 0.0;
+#pragma unroll
+              for (int q = 0; q < PPL; ++q) {
+                tr[0][q] = fma(sv, vr[u].v[q], tr[0][q]);
+                ti[0][q] = fma(sv, vi[u].v[q], ti[0][q]);
+              }
+            }
           }
         }
       } else {
         double *hw = hs[wave];
-        constexpr int CH = U * BB;
-        constexpr int NH = (CH + 63) / 64;
+        constexpr int CH = U * BB;               // H_hat entries per chunk (then as many of S)
+        constexpr int NH = (NM * CH + 63) / 64;
         for (int64_t nz = beg; nz < end; nz += U) {
           // U blocks per chunk; the value and column arrays carry kStepPad zero
           // blocks past nnzb, and blocks past the row's end get no FMAs
@@ -120,6 +135,7 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
           for (int k = 0; k < NH; ++k) {
             const int e = k * 64 + lane;
             if (e < CH) hv[k] = a.hval[nz * BB + e];
+            else if (HS && e < NM * CH) hv[k] = a.sval[nz * BB + (e - CH)];
           }
           int64_t J[U];
 #pragma unroll
@@ -136,7 +152,7 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
 #pragma unroll
           for (int k = 0; k < NH; ++k) {
             const int e = k * 64 + lane;
-            if (e < CH) hw[e] = hv[k];
+            if (e < NM * CH) hw[e] = hv[k];
           }
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
@@ -154,6 +170,14 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
                     sr[i][q] = fma(h, vr[u][j].v[q], sr[i][q]);
                     si[i][q] = fma(h, vi[u][j].v[q], si[i][q]);
                   }
+                  if constexpr (HS) {
+                    const double sv = hw[CH + u * BB + i * BD + j];
+#pragma unroll
+                    for (int q = 0; q < PPL; ++q) {
+                      tr[i][q] = fma(sv, vr[u][j].v[q], tr[i][q]);
+                      ti[i][q] = fma(sv, vi[u][j].v[q], ti[i][q]);
+                    }
+                  }
                 }
             }
           }
@@ -162,11 +186,22 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
 #pragma unroll
       for (int i = 0; i < BD; ++i) {
         const int64_t off = (I * BD + i) * sp + c0;
-        const VecN<double, PPL> ar = ldv<double, PPL>(xr + off), ai = ldv<double, PPL>(xi + off);
+        VecN<double, PPL> ar, ai;
+        if constexpr (HS) {
+#pragma unroll
+          for (int q = 0; q < PPL; ++q) {
+            ar.v[q] = tr[i][q];
+            ai.v[q] = ti[i][q];
+          }
+        } else {
+          ar = ldv<double, PPL>(xr + off);
+          ai = ldv<double, PPL>(xi + off);
+        }
         VecN<double, PPL> o_r, o_i;
 #pragma unroll
         for (int q = 0; q < PPL; ++q) {
-          // (h - z) x:  re = h xr - zr xr + zi xi,  im = h xi - zr xi - zi xr
+          // (h - z m) x with m x = (ar, ai) = x (S = I) or S x:
+          //   re = h xr - zr ar + zi ai,  im = h xi - zr ai - zi ar
           const double vr = fma(zi, ai.v[q], fma(-zr, ar.v[q], sr[i][q]));
           const double vi = fma(-zi, ar.v[q], fma(-zr, ai.v[q], si[i][q]));
           o_r.v[q] = vr;
@@ -183,17 +218,22 @@ __global__ __launch_bounds__(kWG) void k_cspmm(CspArgs a) {
 
 namespace {
 
-// u: neighbours per chunk (1x1: 4 or 8; 9x9: blocks per chunk, 1 or 2)
-const void *select_cspmm(int bd, int ppl, int u) {
+template <bool HS>
+const void *select_cspmm_t(int bd, int ppl, int u) {
   if (bd == 1) {
-    if (u == 8) return ppl == 2 ? (const void *)k_cspmm<1, 2, 8> : (const void *)k_cspmm<1, 1, 8>;
-    return ppl == 2 ? (const void *)k_cspmm<1, 2, 4> : (const void *)k_cspmm<1, 1, 4>;
+    if (u == 8) return ppl == 2 ? (const void *)k_cspmm<1, 2, 8, HS> : (const void *)k_cspmm<1, 1, 8, HS>;
+    return ppl == 2 ? (const void *)k_cspmm<1, 2, 4, HS> : (const void *)k_cspmm<1, 1, 4, HS>;
   }
   if (bd == 9) {
-    if (u == 2) return ppl == 2 ? (const void *)k_cspmm<9, 2, 2> : (const void *)k_cspmm<9, 1, 2>;
-    return ppl == 2 ? (const void *)k_cspmm<9, 2, 1> : (const void *)k_cspmm<9, 1, 1>;
+    if (u == 2) return ppl == 2 ? (const void *)k_cspmm<9, 2, 2, HS> : (const void *)k_cspmm<9, 1, 2, HS>;
+    return ppl == 2 ? (const void *)k_cspmm<9, 2, 1, HS> : (const void *)k_cspmm<9, 1, 1, HS>;
   }
   return nullptr;
+}
+
+// u: neighbours per chunk (1x1: 4 or 8; 9x9: blocks per chunk, 1 or 2); hs: with S
+const void *select_cspmm(int bd, int ppl, int u, bool hs) {
+  return hs ? select_cspmm_t<true>(bd, ppl, u) : select_cspmm_t<false>(bd, ppl, u);
 }
 
 // rows [lo, hi) of workgroup b when n rows are split over gridDim.x workgroups
@@ -234,8 +274,8 @@ struct ColLanes {
 
 }  // namespace
 
-int cspmm_blocks_per_cu(int bd, int ppl, int u) {
-  const void *f = select_cspmm(bd, ppl, u);
+int cspmm_blocks_per_cu(int bd, int ppl, int u, bool hs) {
+  const void *f = select_cspmm(bd, ppl, u, hs);
   if (!f) return 0;
   int nb = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWG, 0) != hipSuccess) return 0;
@@ -243,7 +283,7 @@ int cspmm_blocks_per_cu(int bd, int ppl, int u) {
 }
 
 hipError_t launch_cspmm(int bd, int ppl, int u, const CspArgs &a, hipStream_t s) {
-  const void *f = select_cspmm(bd, ppl, u);
+  const void *f = select_cspmm(bd, ppl, u, a.sval != nullptr);
   if (!f || a.sp % (64 * ppl) != 0 || a.grid % 8 != 0 || a.grid <= 0) return hipErrorInvalidValue;
   CspArgs args = a;
   void *kargs[] = {&args};
@@ -336,6 +376,7 @@ __global__ __launch_bounds__(kWG) void k_cx_dir(const double *__restrict__ sv, d
 
 // partials of y_c . a_c and y_c . b_c; with acc: acc += wr a - wi b (= Re[(wr + i wi)(a + i b)])
 __global__ __launch_bounds__(kWG) void k_cx_pdot(const uint64_t *sgn, const double *rden,
+                                                 const double *__restrict__ yd,
                                                  const double *__restrict__ av,
                                                  const double *__restrict__ bv, int64_t n, int sp,
                                                  double *__restrict__ acc, double wr, double wi,
@@ -349,7 +390,7 @@ __global__ __launch_bounds__(kWG) void k_cx_pdot(const uint64_t *sgn, const doub
     double sa = 0.0, sb = 0.0;
     for (int64_t i = lo + cl.lr; i < hi; i += cl.nl) {
       const int64_t e = i * sp + c;
-      const double y = probe_value(sgn, rden, i, sp, c);
+      const double y = yd ? yd[e] : probe_value(sgn, rden, i, sp, c);
       const double a = av[e], b = bv[e];
       sa = fma(y, a, sa);
       sb = fma(y, b, sb);
@@ -393,9 +434,9 @@ __global__ __launch_bounds__(kWG) void k_cgls_scalars(double *__restrict__ sc, i
 
 // N, E, F of the rational estimate (one workgroup, fixed order):
 //   per column c:  N_c = f0 m0 + 2 Re sum_k cn_k rho_kc
-//                  E_c = f0 (h1 m1 + h0 m0) + ew m0 + 2 Re sum_k ce_k rho_kc
-//                  F_c = g1 (h1 m1 + h0 m0) + g0 m0 + 2 Re sum_k cf_k rho_kc
-// with r^T H r = h1 m1 + h0 m0 (m0 = r.r, m1 = r.H_hat r), rho_kc = r_c . x_kc and
+//                  E_c = f0 h + ew m0 + 2 Re sum_k ce_k rho_kc
+//                  F_c = g1 h + g0 m0 + 2 Re sum_k cf_k rho_kc
+// with m0 = r.r, h = (H r).(S^{-1} r) (S = I: r.H r), rho_kc = (S r_c) . x_kc and
 // coef = [cn | ce | cf] complex per pole; out3 = sum_c w_c (N_c, E_c, F_c).
 __global__ __launch_bounds__(kWG) void k_rational_traces(const double *__restrict__ rho,
                                                          const double *__restrict__ m01,
@@ -405,8 +446,7 @@ __global__ __launch_bounds__(kWG) void k_rational_traces(const double *__restric
                                                          double *__restrict__ out3) {
   double acc[3] = {0.0, 0.0, 0.0};
   for (int c = threadIdx.x; c < sp; c += blockDim.x) {
-    const double m0 = m01[c], m1 = m01[sp + c];
-    const double rhr = k.h1 * m1 + k.h0 * m0;
+    const double m0 = m01[c], rhr = m01[sp + c];
     double sn = 0.0, se = 0.0, sf = 0.0;
     for (int p = 0; p < n_poles; ++p) {
       const double pr = rho[(int64_t)p * 2 * sp + c], pi = rho[(int64_t)p * 2 * sp + sp + c];
@@ -469,11 +509,25 @@ hipError_t launch_cx_dir(const double *sv, double *p, double *x, const double *a
   return hipGetLastError();
 }
 
-hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double *a, const double *b,
-                          int64_t n, int sp, double *acc, double wr, double wi, double *part_a,
-                          double *part_b, hipStream_t s) {
-  hipLaunchKernelGGL(k_cx_pdot, dim3(cg_nparts(n)), dim3(kWG), 0, s, sgn, rden, a, b, n, sp, acc,
-                     wr, wi, part_a, part_b);
+hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double *yd, const double *a,
+                          const double *b, int64_t n, int sp, double *acc, double wr, double wi,
+                          double *part_a, double *part_b, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_pdot, dim3(cg_nparts(n)), dim3(kWG), 0, s, sgn, rden, yd, a, b, n, sp,
+                     acc, wr, wi, part_a, part_b);
+  return hipGetLastError();
+}
+
+// dst = alpha * src over n elements
+__global__ __launch_bounds__(kWG) void k_cx_scale(const double *__restrict__ src,
+                                                  double *__restrict__ dst, int64_t n,
+                                                  double alpha) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    dst[e] = alpha * src[e];
+}
+
+hipError_t launch_cx_scale(const double *src, double *dst, int64_t n, double alpha, hipStream_t s) {
+  hipLaunchKernelGGL(k_cx_scale, dim3(ew_blocks(n)), dim3(kWG), 0, s, src, dst, n, alpha);
   return hipGetLastError();
 }
 

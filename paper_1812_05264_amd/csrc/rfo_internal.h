@@ -195,6 +195,7 @@ struct CspArgs {
   const int64_t *row_ptr;
   const int32_t *col;
   const double *hval;      // H_hat blocks (FP64)
+  const double *sval;      // overlap S blocks (out = H_hat x - z S x), or nullptr (S = I)
   const double *x;         // complex input (two planes)
   double *out;             // complex output (two planes), not aliasing x
   double zr, zi;           // the shift z
@@ -208,7 +209,7 @@ struct CspArgs {
 };
 // u: neighbours per chunk (1x1: 4 or 8; 9x9: blocks per chunk, 1 or 2)
 hipError_t launch_cspmm(int bd, int ppl, int u, const CspArgs &a, hipStream_t s);
-int cspmm_blocks_per_cu(int bd, int ppl, int u);
+int cspmm_blocks_per_cu(int bd, int ppl, int u, bool hs);
 // dre = scale * y (probes), dim = 0 when non-null
 hipError_t launch_cx_fill(const uint64_t *sgn, const double *rden, int64_t n, int sp, double scale,
                           double *dre, double *dim, hipStream_t s);
@@ -221,17 +222,19 @@ hipError_t launch_cx_update(double *r, const double *q, const double *alpha, int
 // x += alpha_c p, then p = s + beta_c p
 hipError_t launch_cx_dir(const double *sv, double *p, double *x, const double *alpha,
                          const double *beta, int64_t n, int sp, hipStream_t s);
-// partials y_c . a_c, y_c . b_c; acc += wr a - wi b when acc != nullptr
-hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double *a, const double *b,
-                          int64_t n, int sp, double *acc, double wr, double wi, double *part_a,
-                          double *part_b, hipStream_t s);
+// partials y_c . a_c, y_c . b_c with y the probes (yd == nullptr) or the plane yd;
+// acc += wr a - wi b when acc != nullptr
+hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double *yd, const double *a,
+                          const double *b, int64_t n, int sp, double *acc, double wr, double wi,
+                          double *part_a, double *part_b, hipStream_t s);
+// dst = alpha * src (n elements)
+hipError_t launch_cx_scale(const double *src, double *dst, int64_t n, double alpha, hipStream_t s);
 // mode 0: gam = ssn, *resmax;  1: alpha = gam / qq;  2: beta = ssn / gam, gam = ssn, *resmax
 hipError_t launch_cgls_scalars(double *sc, int sp, int mode, double *resmax, hipStream_t s);
 struct RationalScalars {
   double f0, ew, g0, g1;   // constant of f, 2 Re sum_k w_k, constant and slope of g
-  double h0, h1;           // r^T H r = h1 r^T H_hat r + h0 r^T r
 };
-// N, E, F from rho [n_poles][2][sp] (r_c . x_kc), m01 [2][sp] (r.r, r.H_hat r),
+// N, E, F from rho [n_poles][2][sp] ((S r_c) . x_kc), m01 [2][sp] (r.r, (H r).(S^{-1} r)),
 // weights and coef [3][n_poles] complex (N, E, F coefficients of rho).
 hipError_t launch_rational_traces(const double *rho, const double *m01, const double *w,
                                   const double *coef, int n_poles, int sp,
