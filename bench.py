@@ -203,7 +203,6 @@ def overlap_leg(args):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     it, so = eng.cg_stats()
-    eng.close()
     out = {"workload": "cu4k with overlap", "atoms": cl.n_atoms, "probes": 128,
            "n_terms": args.ov_terms, "interval_eV": [round(a, 4), round(b, 4)],
            "seconds": round(dt, 4), "cg_solves": so - so0,
@@ -211,7 +210,47 @@ def overlap_leg(args):
            "ms_per_chebyshev_step": round(dt * 1e3 / max(1, args.ov_terms - 1), 3), "N": g["N"]}
     print(f"[bench] overlap cu4k: {dt:.3f} s for {args.ov_terms} terms, "
           f"{out['cg_iterations_per_solve']} CG iterations per solve", flush=True)
+    if args.ov_rat_eps > 0:
+        out["rational"] = overlap_rational(eng, cl, a, b, args.ov_rat_eps)
+    eng.close()
     return out
+
+
+def overlap_rational(eng, cl, a, b, eps, T=0.05, mu=1.165):
+    """Rational against Chebyshev with the overlap at matched tolerance eps: the
+    Chebyshev length from the paper's error model on the pencil interval, the
+    fewest contour-fit nodes whose error of f on [a, b] is <= eps, CGLS to relative
+    residual eps (each CGLS product applies H and S; S^-1 by CG for P, Q)."""
+    import numpy as np
+    import torch
+    import paper_1812_05264_amd as pkg
+    p = int(np.ceil(np.log(1.0 / eps) * (b - a) / (6.4 * T)))
+    x = np.linspace(a, b, 20001)
+    f_exact = 1.0 - np.tanh((x - mu) / (2.0 * T))
+    for nodes in range(1, 129):
+        fit = pkg.rational_fit(nodes, T, mu, a, b)
+        r = fit["f0"] + 2.0 * np.real((1.0 / (x[:, None] - fit["poles"])) @ fit["res_f"])
+        if np.max(np.abs(r - f_exact)) <= eps:
+            break
+    else:
+        raise RuntimeError("no fit within 128 nodes")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g_p = eng.fermi_moments(T, mu, p, density=True)
+    torch.cuda.synchronize()
+    t_p = time.perf_counter() - t0
+    it0, _ = eng.rational_stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g_r = eng.rational(mu, fit, tol=eps, max_iter=200000, density=True)
+    torch.cuda.synchronize()
+    t_r = time.perf_counter() - t0
+    it1, _ = eng.rational_stats()
+    print(f"[bench] overlap cu4k eps={eps:g}: poly {p} terms {t_p:.3f} s, rational "
+          f"{2 * nodes} poles {t_r:.3f} s ({it1 - it0} CGLS iterations)", flush=True)
+    return {"eps": eps, "poly_terms": p, "poly_s": round(t_p, 4), "rat_poles": 2 * nodes,
+            "rat_s": round(t_r, 4), "cgls_iterations": int(it1 - it0),
+            "dN_per_atom_rat_vs_poly": abs(g_r["N"] - g_p["N"]) / cl.n_atoms}
 
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
@@ -377,6 +416,8 @@ def main():
                     help="coloring radius (A) of a multi-color probe energy_force run (0 = skip)")
     ap.add_argument("--ov-terms", type=int, default=200,
                     help="terms of the overlap (nonorthogonal basis) leg (0 = skip)")
+    ap.add_argument("--ov-rat-eps", type=float, default=1e-3,
+                    help="overlap leg: rational vs Chebyshev at this tolerance (0: off)")
     ap.add_argument("--cluster-steps", type=int, default=1,
                     help="step throughput legs on the Cu-like clusters (0 = skip)")
     ap.add_argument("--rat-eps", default="1e-3",
@@ -385,6 +426,8 @@ def main():
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
                     help="run only the energy_force leg (for profiling)")
+    ap.add_argument("--only-overlap", action="store_true",
+                    help="run only the overlap leg")
     ap.add_argument("--only-rational", action="store_true",
                     help="run only the rational-vs-polynomial leg (for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -415,6 +458,9 @@ def main():
         return
     if args.only_rational:
         print(json.dumps({"rational": rational_leg(args)}))
+        return
+    if args.only_overlap:
+        print(json.dumps({"overlap": overlap_leg(args)}))
         return
 
     import numpy as np
