@@ -155,6 +155,9 @@ struct Plan {
   int n_pt_step;   // probe tiles of the step kernel (BF16: tiles of 16 * ntiles probes)
   int ntiles;      // BF16: MFMA column tiles per wave
   size_t vec_elems;
+  // bytes per vector slot: the vector, and in BF16 mode its BF16 copy (the
+  // operand the steps gather) right after it
+  size_t slot_bytes;
 };
 
 Plan make_plan(const rfo_ctx *c) {
@@ -192,14 +195,20 @@ Plan make_plan(const rfo_ctx *c) {
   pl.ntiles = 0;
   int occ = 1;
   if (c->prec == RFO_BF16) {
+    // 4 MFMA column tiles (64 probes) per wave, 2 blocks per chunk: measured best
+    // (wider tiles or chunks cost more registers than the loads they add in flight)
     pl.ntiles = 4;
-    pl.rpi = 1;
+    pl.rpi = 2;
     if (const char *env = getenv("RFO_NTILES")) {
       const int t = atoi(env);
       if ((t == 4 || t == 8 || t == 16) && c->sp % (16 * t) == 0) pl.ntiles = t;
     }
     pl.n_pt_step = c->sp / (16 * pl.ntiles);
-    if (pl.ntiles == 16) pl.rpi = 1;
+    if (const char *env = getenv("RFO_BF16_U")) {
+      const int u = atoi(env);
+      if (u == 1 || u == 2 || u == 4) pl.rpi = u;
+    }
+    if (pl.ntiles == 16 && pl.rpi > 2) pl.rpi = 2;
     occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi));
   } else {
     occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi));
@@ -214,6 +223,7 @@ Plan make_plan(const rfo_ctx *c) {
   grid = std::max<int64_t>(8, grid / 8 * 8);
   pl.grid = (int)grid;
   pl.vec_elems = (size_t)c->n * (size_t)c->sp;
+  pl.slot_bytes = pl.vec_elems * (pl.vt_bytes + (c->prec == RFO_BF16 ? 2 : 0));
   return pl;
 }
 
@@ -259,12 +269,24 @@ hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::StepArgs
   // three accumulator terms need y_{k-1}, which the first pass does not have
   if (a.acc_terms < 0 || a.acc_terms > 3 || (a.acc_terms == 3 && a.c2 == 0.0))
     return hipErrorInvalidValue;
-  if (c->prec == RFO_BF16) return rfo::launch_step_bf16(pl.ntiles, a, c->stream);
+  if (c->prec == RFO_BF16) {
+    // x and out are vector slots; their BF16 copies follow the FP32 vectors
+    rfo::StepArgs b = a;
+    b.xb = static_cast<const char *>(a.x) + pl.vec_elems * sizeof(float);
+    b.outb = static_cast<char *>(a.out) + pl.vec_elems * sizeof(float);
+    return rfo::launch_step_bf16(pl.ntiles, b, c->stream);
+  }
   return rfo::launch_step(c->bd, kernel_precision(c), pl.ppl, a, c->stream);
 }
 
+// y = scale r into a vector slot (and its BF16 copy in BF16 mode)
+hipError_t launch_init_slot(const rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
+  a.outb = c->prec == RFO_BF16 ? static_cast<char *>(a.out) + pl.vec_elems * sizeof(float) : nullptr;
+  return rfo::launch_init(kernel_precision(c), a, c->stream);
+}
+
 char *vec_at(rfo_ctx *c, const Plan &pl, DevBuf &b, int64_t i) {
-  return static_cast<char *>(b.p) + (size_t)i * pl.vec_elems * pl.vt_bytes;
+  return static_cast<char *>(b.p) + (size_t)i * pl.slot_bytes;
 }
 
 hipEvent_t next_event(rfo_ctx *c, size_t idx) {
@@ -384,7 +406,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
       if (k == q * m) which = 1;
       if (which >= 0) {
         char *dst = vec_at(ctx, pl, *ck->store, 2 * (q - 1) + which);
-        HIPCHK(hipMemcpyAsync(dst, src, pl.vec_elems * pl.vt_bytes, hipMemcpyDeviceToDevice,
+        HIPCHK(hipMemcpyAsync(dst, src, pl.slot_bytes, hipMemcpyDeviceToDevice,
                               ctx->stream));
       }
     }
@@ -398,7 +420,7 @@ int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bool use_
   ia.acc = accp;
   ia.alpha = coef;  // alpha^f_0
   ia.part = ring;
-  HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+  HIPCHK(launch_init_slot(ctx, pl, ia));
   HIPCHK(rfo::launch_moment_reduce(ring, pl.ring, 0, 1, pl.grid, ctx->sp, mom, 0, tol, flags, 0,
                                    ctx->stream));
   TRY(save(0, A));
@@ -866,7 +888,7 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
   TRY(prepare_call(ctx, T, mu, n_terms, pl));
   const bool dens = density_out != nullptr;
   // vector slots: y pair; with an overlap also t and the CG vectors r, p, q
-  TRY(ensure(ctx, ctx->vec, (ctx->has_s ? 6 : 2) * pl.vec_elems * pl.vt_bytes));
+  TRY(ensure(ctx, ctx->vec, (ctx->has_s ? 6 : 2) * pl.slot_bytes));
   if (dens) TRY(ensure(ctx, ctx->acc, pl.vec_elems * pl.vt_bytes));
   if (ctx->has_s) TRY(ensure_cg(ctx));
   size_t n_events = 0;
@@ -973,10 +995,10 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   const int64_t Q = (K + m - 1) / m;
   // vector slots: ys [m + 2] | zs [m + 2] | checkpoints [2 (Q - 1)]
   const int64_t n_ys = m + 2, n_zs = m + 2, n_ck = Q > 1 ? 2 * (Q - 1) : 0;
-  TRY(ensure(ctx, ctx->vec, (size_t)(n_ys + n_zs + n_ck) * pl.vec_elems * pl.vt_bytes));
+  TRY(ensure(ctx, ctx->vec, (size_t)(n_ys + n_zs + n_ck) * pl.slot_bytes));
   DevBuf ckview;
   ckview.p = vec_at(ctx, pl, ctx->vec, n_ys + n_zs);
-  ckview.bytes = (size_t)n_ck * pl.vec_elems * pl.vt_bytes;
+  ckview.bytes = (size_t)n_ck * pl.slot_bytes;
   Checkpoints ck;
   ck.m = m;
   ck.Q = Q;
@@ -1000,7 +1022,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   for (int64_t j = 2; j <= K; ++j)
     if (2 * j - 1 <= p - 1) b[1] -= beta[2 * j - 1];
 
-  const size_t vb = pl.vec_elems * pl.vt_bytes;
+  const size_t vb = pl.slot_bytes;
   auto ys = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, t); };
   auto zs = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, n_ys + t); };
   auto cka = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_ys + n_zs + 2 * (q - 1)); };
@@ -1019,7 +1041,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
       ia.scale = nullptr;
       ia.acc = nullptr;
       ia.part = nullptr;
-      HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+      HIPCHK(launch_init_slot(ctx, pl, ia));
     } else {
       HIPCHK(hipMemcpyAsync(ys(0), ckb(q), vb, hipMemcpyDeviceToDevice, ctx->stream));
     }
@@ -1080,9 +1102,9 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
     sd.bd = ctx->bd;
     sd.sp = ctx->sp;
     sd.xbase = zs(0);
-    sd.xstride = (int64_t)pl.vec_elems;
+    sd.xstride = (int64_t)(pl.slot_bytes / pl.vt_bytes);
     sd.ybase = ys(0);
-    sd.ystride = (int64_t)pl.vec_elems;
+    sd.ystride = (int64_t)(pl.slot_bytes / pl.vt_bytes);
     sd.w = P<double>(ctx->w);
     sd.count = (int)len;
     sd.j0 = j0;
@@ -1139,13 +1161,13 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   const int64_t Q = P1 > 0 ? (P1 + m - 1) / m : 0;
   // vector slots: ys [m] | zs [m + 2] | checkpoints [2 (Q - 1)]
   const int64_t n_ys = m, n_zs = m + 2, n_ck = Q > 1 ? 2 * (Q - 1) : 0;
-  TRY(ensure(ctx, ctx->vec, (size_t)(n_ys + n_zs + n_ck) * pl.vec_elems * pl.vt_bytes));
+  TRY(ensure(ctx, ctx->vec, (size_t)(n_ys + n_zs + n_ck) * pl.slot_bytes));
   const double *beta = P<double>(ctx->coef) + 2 * p;
 
   // forward pass (rolling pair in ys[0], ys[1]) with checkpoints y_{qm-1}, y_{qm}
   DevBuf ckview;
   ckview.p = vec_at(ctx, pl, ctx->vec, n_ys + n_zs);
-  ckview.bytes = (size_t)n_ck * pl.vec_elems * pl.vt_bytes;
+  ckview.bytes = (size_t)n_ck * pl.slot_bytes;
   Checkpoints ck;
   ck.m = m;
   ck.Q = Q;
@@ -1159,7 +1181,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   if (P1 == 0) {
     HIPCHK(hipMemsetAsync(ctx->G.p, 0, gbytes, ctx->stream));
   } else {
-    const size_t vb = pl.vec_elems * pl.vt_bytes;
+    const size_t vb = pl.slot_bytes;
     auto ys = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, t); };
     auto zs = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, n_ys + t); };
     auto cka = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_ys + n_zs + 2 * (q - 1)); };
@@ -1176,7 +1198,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
         ia.scale = nullptr;
         ia.acc = nullptr;
         ia.part = nullptr;
-        HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+        HIPCHK(launch_init_slot(ctx, pl, ia));
       } else {
         HIPCHK(hipMemcpyAsync(ys(0), ckb(q), vb, hipMemcpyDeviceToDevice, ctx->stream));
       }
@@ -1206,7 +1228,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
           ia.scale = beta + (p - 1);
           ia.acc = nullptr;
           ia.part = nullptr;
-          HIPCHK(rfo::launch_init(kp, ia, ctx->stream));
+          HIPCHK(launch_init_slot(ctx, pl, ia));
         } else {
           sa.x = zs(t + 1);
           sa.prev = (i == p - 2) ? nullptr : zs(t + 2);
@@ -1228,9 +1250,9 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       a.bd = ctx->bd;
       a.sp = ctx->sp;
       a.xbase = zs(0);
-      a.xstride = (int64_t)pl.vec_elems;
+      a.xstride = (int64_t)(pl.slot_bytes / pl.vt_bytes);
       a.ybase = ys(0);
-      a.ystride = (int64_t)pl.vec_elems;
+      a.ystride = (int64_t)(pl.slot_bytes / pl.vt_bytes);
       a.w = P<double>(ctx->w);
       a.count = (int)len;
       a.j0 = j0;
@@ -1433,7 +1455,7 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   // planes: x, r, p, q, s (complex), the P r accumulator, and S r with an overlap
   TRY(ensure(ctx, ctx->rat, (size_t)(ctx->has_s ? 12 : 11) * plane * sizeof(double)));
   if (ctx->has_s) {
-    TRY(ensure(ctx, ctx->vec, 6 * pl.vec_elems * pl.vt_bytes));  // CG work slots
+    TRY(ensure(ctx, ctx->vec, 6 * pl.slot_bytes));  // CG work slots
     TRY(ensure_cg(ctx));
   }
   TRY(ensure(ctx, ctx->rat_part, (size_t)2 * w.nparts * sp * sizeof(double)));

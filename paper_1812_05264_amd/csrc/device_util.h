@@ -141,6 +141,12 @@ __device__ __forceinline__ VecN<VT, N> add_terms(VecN<VT, N> av, int m, const VT
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// BF16 bits of an FP32 value, rounded to nearest even.
+__device__ __forceinline__ unsigned short bf16_bits(float f) {
+  __bf16 b = (__bf16)f;
+  return __builtin_bit_cast(unsigned short, b);
+}
+
 // Load through the constant address space: with a wave-uniform address this
 // becomes a scalar (SMEM) load.  Only for data that no kernel of the same launch
 // writes.

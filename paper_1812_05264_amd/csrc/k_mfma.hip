@@ -10,9 +10,12 @@
 // Lane l supplies A[l%16][4(l/16)+kk], B[4(l/16)+kk][l%16] for kk < 4 and holds
 // D[4(l/16)+i][l%16] for i < 4.  A wave covers 16*NT probes as NT MFMA tiles;
 // column n of tile t is probe p0 + n*NT + t, so a lane reads and writes NT
-// consecutive probes of a row with one vector access.  Operands are rounded to
-// BF16 (round to nearest even); accumulation, the recurrence
-// out = c1 D + c2 prev + beta r and the vectors stay FP32; moments are FP64.
+// consecutive probes of a row with one vector access.  Operands are BF16 (round
+// to nearest even); accumulation, the recurrence out = c1 D + c2 prev + beta r
+// and the vectors stay FP32; moments are FP64.  Every FP32 vector has a BF16
+// copy (rounded the same way) that its producer writes beside it: the gathered
+// B operands come from that copy, half the bytes of the FP32 rows, and only
+// the nine real rows of X_J are loaded (lanes of rows 9..15 load nothing).
 //
 // A operands are pre-packed per block: entry g*9 + m (g < 3, m < 9) holds
 // H_hat[m][4g .. 4g+3] as four BF16 (zero where the column index exceeds 8);
@@ -27,11 +30,6 @@ namespace {
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short bf16_bits(float f) {
-  __bf16 b = (__bf16)f;
-  return __builtin_bit_cast(short, b);
-}
-
 }  // namespace
 
 template <int NT, int U, bool NTH, int MODE>
@@ -43,8 +41,10 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   const int sp = a.sp;
   const int nw = sp >> 6;
   const float *__restrict__ x = static_cast<const float *>(a.x);
+  const unsigned short *__restrict__ xb = static_cast<const unsigned short *>(a.xb);
   const float *prev = static_cast<const float *>(a.prev);
   float *out = static_cast<float *>(a.out);
+  unsigned short *outb = static_cast<unsigned short *>(a.outb);
   float *acc = static_cast<float *>(a.acc);
   const uint2 *hpack = static_cast<const uint2 *>(a.hval);
   const bool has_prev = a.c2 != 0.0;
@@ -128,10 +128,7 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
       for (int t = 0; t < NT; ++t) d[t] = f4{0.f, 0.f, 0.f, 0.f};
       for (int64_t nz0 = beg; nz0 < end; nz0 += U) {
         s4 av[U];
-        VecN<float, NT> xr[U][4];
-        // every lane loads (rows and entries past the block are clamped to valid
-        // addresses and zeroed afterwards), so no load sits in a divergent branch
-        // and all of them are in flight together
+        VecN<unsigned short, NT> xr[U][4];
         const bool a_live = g < 3 && n < 9;
         const int a_idx = a_live ? g * 9 + n : 0;
 #pragma unroll
@@ -142,51 +139,57 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
           av[u] = a_live ? s4{(short)(p.x & 0xffff), (short)(p.x >> 16), (short)(p.y & 0xffff),
                               (short)(p.y >> 16)}
                          : s4{0, 0, 0, 0};
+          // K rows 9..15 are zero: their lanes load nothing
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
-            const int rr = min(4 * g + kk, 8);
-            xr[u][kk] = ldv<float, NT>(x + (J * 9 + rr) * sp + cp);
+            const int rr = 4 * g + kk;
+            if (rr < 9) {
+              xr[u][kk] = ldv<unsigned short, NT>(xb + (J * 9 + rr) * sp + cp);
+            } else {
+#pragma unroll
+              for (int t = 0; t < NT; ++t) xr[u][kk].v[t] = 0;
+            }
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-          for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-            for (int t = 0; t < NT; ++t)
-              xr[u][kk].v[t] = (4 * g + kk < 9) ? xr[u][kk].v[t] : 0.f;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (nz0 + u < end) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-              const s4 bv = s4{bf16_bits(xr[u][0].v[t]), bf16_bits(xr[u][1].v[t]),
-                               bf16_bits(xr[u][2].v[t]), bf16_bits(xr[u][3].v[t])};
+              const s4 bv = s4{(short)xr[u][0].v[t], (short)xr[u][1].v[t], (short)xr[u][2].v[t],
+                               (short)xr[u][3].v[t]};
               d[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[u], bv, d[t], 0, 0, 0);
             }
           }
         }
       }
-      // epilogue: lane holds rows 4g+i (valid below 9) for probes cp .. cp+NT-1;
-      // streamed inputs of all four rows are requested first (clamped rows)
-      VecN<float, NT> pv4[4], xs4[4];
-      uint64_t sw4[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
+      // epilogue: lane holds rows 4g+i (valid below 9) for probes cp .. cp+NT-1.
+      // The streamed inputs are loaded row by row: requesting all four rows first
+      // holds more registers and measured slower (occupancy 3 instead of 4).
+      constexpr int NPRE = 1;
+      VecN<float, NT> pv4[NPRE], xs4[NPRE];
+      uint64_t sw4[NPRE];
+      auto load_row = [&](int i, int slot) {
         const int64_t row = I * 9 + min(4 * g + i, 8);
-        if (has_prev) pv4[i] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
-                                   : ldv<float, NT>(prev + row * sp + cp);
-        if (m >= 2 || DBL) xs4[i] = ldv<float, NT>(x + row * sp + cp);
-        if (need_r && a.sgn) sw4[i] = a.sgn[row * nw + (cp >> 6)];
+        if (has_prev) pv4[slot] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
+                                      : ldv<float, NT>(prev + row * sp + cp);
+        if (m >= 2 || DBL) xs4[slot] = ldv<float, NT>(x + row * sp + cp);
+        if (need_r && a.sgn) sw4[slot] = a.sgn[row * nw + (cp >> 6)];
+      };
+      if constexpr (NPRE == 4) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) load_row(i, i);
       }
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int rr = 4 * g + i;
         if (rr >= 9) continue;
+        const int si = NPRE == 4 ? i : 0;
+        if constexpr (NPRE == 1) load_row(i, 0);
         const int64_t row = I * 9 + rr;
         const int64_t off = row * sp + cp;
-        const VecN<float, NT> pv = pv4[i];
-        const uint64_t sw = sw4[i];
+        const VecN<float, NT> pv = pv4[si];
+        const uint64_t sw = sw4[si];
         VecN<float, NT> sv[3];
         if (SRC) {
 #pragma unroll
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
           if (mom_on) {
             if (DBL) {
               mom[t] = fma((double)v, (double)v, mom[t]);
-              mom2[t] = fma((double)v, (double)xs4[i].v[t], mom2[t]);
+              mom2[t] = fma((double)v, (double)xs4[si].v[t], mom2[t]);
             } else {
               mom[t] = fma(rq, (double)v, mom[t]);
             }
@@ -220,9 +223,13 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
         }
         if (NTH) stv_nt<float, NT>(out + off, o);
         else stv<float, NT>(out + off, o);
+        VecN<unsigned short, NT> ob;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) ob.v[t] = bf16_bits(o.v[t]);
+        stv<unsigned short, NT>(outb + off, ob);
         if (m > 0) {
           VecN<float, NT> avv = NTH ? ldv_nt<float, NT>(acc + off) : ldv<float, NT>(acc + off);
-          avv = add_terms<float, NT>(avv, m, al, pv, xs4[i], o);
+          avv = add_terms<float, NT>(avv, m, al, pv, xs4[si], o);
           if (NTH) stv_nt<float, NT>(acc + off, avv);
           else stv<float, NT>(acc + off, avv);
         }
@@ -248,7 +255,7 @@ __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hh
     for (int kk = 0; kk < 4; ++kk) {
       const int col = 4 * gg + kk;
       const float f = col < 9 ? (float)hhat[nz * 81 + m * 9 + col] : 0.f;
-      v[kk] = (unsigned short)bf16_bits(f);
+      v[kk] = bf16_bits(f);
     }
     hpack[e] = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
                           (unsigned)v[2] | ((unsigned)v[3] << 16));
@@ -266,9 +273,12 @@ const void *select_bf16(int nt_tiles, int u, int mode) {
                        : (const void *)k_step9_bf16<T, UU, true, 0>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
+  RFO_BF16_CASE(4, 4)
   RFO_BF16_CASE(8, 1)
   RFO_BF16_CASE(8, 2)
+  RFO_BF16_CASE(8, 4)
   RFO_BF16_CASE(16, 1)
+  RFO_BF16_CASE(16, 2)
 #undef RFO_BF16_CASE
   return nullptr;
 }

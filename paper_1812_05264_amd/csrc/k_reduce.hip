@@ -10,7 +10,10 @@
 //
 // One wave owns one block: lanes run along the contraction index (probes), each
 // lane keeps all bd*bd partial sums in registers over the whole contraction, and
-// a fixed butterfly reduces them at the end (bitwise reproducible).
+// a fixed butterfly reduces them at the end (bitwise reproducible).  Workgroups
+// are remapped so that each XCD takes one contiguous range of the block list:
+// the waves in flight on an XCD then read the vectors of a narrow band of block
+// rows, which that XCD's L2 holds.
 #include "device_util.h"
 #include "rfo_internal.h"
 
@@ -20,7 +23,7 @@ template <int BD, typename VT, int PPL, bool SYM>
 __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  const int64_t widx = (int64_t)blockIdx.x * kWaves + wave;
+  const int64_t widx = (int64_t)xcd_logical(blockIdx.x, gridDim.x) * kWaves + wave;
   const int64_t total = a.nzlist ? a.nlist : a.nnzb;
   if (widx >= total) return;
   const int64_t nz = a.nzlist ? sld(a.nzlist + widx) : widx;

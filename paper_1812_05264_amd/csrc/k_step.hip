@@ -506,6 +506,14 @@ __global__ __launch_bounds__(kWG) void k_init(InitArgs a) {
         }
         stv<VT, PPL>(out + off, o);
         if (acc) stv<VT, PPL>(acc + off, av);
+        if constexpr (sizeof(VT) == 4) {
+          if (a.outb) {
+            VecN<unsigned short, PPL> ob;
+#pragma unroll
+            for (int q = 0; q < PPL; ++q) ob.v[q] = bf16_bits((float)o.v[q]);
+            stv<unsigned short, PPL>(static_cast<unsigned short *>(a.outb) + off, ob);
+          }
+        }
       }
     }
   }

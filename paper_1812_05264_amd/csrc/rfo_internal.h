@@ -31,6 +31,8 @@ struct StepArgs {
   const void *x;           // y_k (gathered)
   const void *prev;        // y_{k-1} (may alias out)
   void *out;               // y_{k+1}
+  const void *xb;          // BF16 steps: BF16 copy of y_k, the operand that is gathered
+  void *outb;              // BF16 steps: BF16 copy of y_{k+1}, written with it
   const uint64_t *sgn;     // [n][sp/64] sign bits (bit 1 = +1), or nullptr
   const double *rden;      // [n][sp] dense probes, or nullptr
   double c1, c2;
@@ -68,6 +70,7 @@ hipError_t launch_step(int bd, int precision, int ppl, const StepArgs &a, hipStr
 // y = scale * r (+ acc = alpha * r, + part = r . y) with the step kernel's decomposition
 struct InitArgs {
   void *out;
+  void *outb;              // FP32 vectors: BF16 copy of out, or nullptr
   const uint64_t *sgn;
   const double *rden;
   const double *scale;     // device scalar, nullptr = 1
