@@ -39,6 +39,10 @@ struct rfo_ctx {
   std::vector<int32_t> col_h;
   DevBuf row_ptr, col, brow, tpos, hraw, h64, h32, hbf16, gscratch, nz_up, nz_low;
   int64_t n_up = 0, n_low = 0;
+  // BF16 steps: K chunks of 16 rows per block row (first chunk of each row,
+  // gathered row J*9 + c and source nz*9 + c of every K row)
+  DevBuf kc_ptr, kc_idx, kc_src;
+  int64_t n_chunks = 0;
 
   // probes
   bool has_r = false;
@@ -75,6 +79,7 @@ struct rfo_ctx {
   ~rfo_ctx() {
     hipSetDevice(device);
     DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch, &nz_up, &nz_low,
+                     &kc_ptr, &kc_idx, &kc_src,
                      &s64, &cg_part, &cg_sc, &GQ, &rat, &rat_part, &rat_sc, &rat_rho, &rat_coef,
                      &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
                      &costab, &small, &flags, &G, &dHdR, &forces};
@@ -199,16 +204,11 @@ Plan make_plan(const rfo_ctx *c) {
     // (wider tiles or chunks cost more registers than the loads they add in flight)
     pl.ntiles = 4;
     pl.rpi = 2;
-    if (const char *env = getenv("RFO_NTILES")) {
-      const int t = atoi(env);
-      if ((t == 4 || t == 8 || t == 16) && c->sp % (16 * t) == 0) pl.ntiles = t;
-    }
     pl.n_pt_step = c->sp / (16 * pl.ntiles);
     if (const char *env = getenv("RFO_BF16_U")) {
       const int u = atoi(env);
       if (u == 1 || u == 2 || u == 4) pl.rpi = u;
     }
-    if (pl.ntiles == 16 && pl.rpi > 2) pl.rpi = 2;
     occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi));
   } else {
     occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi));
@@ -232,6 +232,10 @@ void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
   a.row_ptr = P<int64_t>(c->row_ptr);
   a.col = P<int32_t>(c->col);
   a.hval = c->prec == RFO_FP64 ? c->h64.p : (c->prec == RFO_FP32 ? c->h32.p : c->hbf16.p);
+  if (c->prec == RFO_BF16) {
+    a.kc_ptr = P<int64_t>(c->kc_ptr);
+    a.kc_idx = P<int32_t>(c->kc_idx);
+  }
   a.sgn = c->signs ? P<uint64_t>(c->sgn) : nullptr;
   a.rden = c->signs ? nullptr : P<double>(c->rden);
   a.nb = c->nb;
@@ -783,10 +787,39 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     HIPCHK(hipMemsetAsync(P<float>(ctx->h32) + nval, 0, npad * sizeof(float), ctx->stream));
   }
   if (precision == RFO_BF16) {
-    const size_t pk = (size_t)27 * 8;  // bytes of one packed block
-    TRY(ensure(ctx, ctx->hbf16, ((size_t)ctx->nnzb + rfo::kStepPad) * pk));
-    HIPCHK(hipMemsetAsync(static_cast<char *>(ctx->hbf16.p) + (size_t)ctx->nnzb * pk, 0,
-                          rfo::kStepPad * pk, ctx->stream));
+    // K chunks: block row I's blocks concatenated along K (9 rows each), cut into
+    // chunks of 16 K rows; K row k of the row is column c = k % 9 of block
+    // nz = row_ptr[I] + k / 9
+    const std::vector<int64_t> &rp = ctx->row_ptr_h;
+    const std::vector<int32_t> &cl = ctx->col_h;
+    if ((int64_t)ctx->nnzb * 9 >= ((int64_t)1 << 31) || ctx->n >= ((int64_t)1 << 31))
+      return fail(ctx, RFO_E_UNSUPPORTED, "BF16 steps index rows with 32 bits");
+    std::vector<int64_t> kp((size_t)ctx->nb + 1, 0);
+    for (int64_t I = 0; I < ctx->nb; ++I) kp[I + 1] = kp[I] + (9 * (rp[I + 1] - rp[I]) + 15) / 16;
+    const int64_t nch = kp[ctx->nb];
+    std::vector<int32_t> kidx((size_t)nch * 16, -1), ksrc((size_t)nch * 16, -1);
+    for (int64_t I = 0; I < ctx->nb; ++I)
+      for (int64_t k = 0; k < 9 * (rp[I + 1] - rp[I]); ++k) {
+        const int64_t nz = rp[I] + k / 9, c = k % 9;
+        kidx[(size_t)(kp[I] * 16 + k)] = (int32_t)((int64_t)cl[nz] * 9 + c);
+        ksrc[(size_t)(kp[I] * 16 + k)] = (int32_t)(nz * 9 + c);
+      }
+    ctx->n_chunks = nch;
+    const size_t nq = (size_t)std::max<int64_t>(nch, 1);
+    TRY(ensure(ctx, ctx->kc_ptr, kp.size() * sizeof(int64_t)));
+    TRY(ensure(ctx, ctx->kc_idx, nq * 16 * sizeof(int32_t)));
+    TRY(ensure(ctx, ctx->kc_src, nq * 16 * sizeof(int32_t)));
+    TRY(ensure(ctx, ctx->hbf16, nq * 36 * 8));
+    HIPCHK(hipMemcpyAsync(ctx->kc_ptr.p, kp.data(), kp.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    if (nch > 0) {
+      HIPCHK(hipMemcpyAsync(ctx->kc_idx.p, kidx.data(), kidx.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(ctx->kc_src.p, ksrc.data(), ksrc.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, ctx->stream));
+    }
+    // the host vectors go out of scope: wait for the copies
+    HIPCHK(hipStreamSynchronize(ctx->stream));
   }
   HIPCHK(hipMemcpyAsync(ctx->hraw.p, values, nval * sizeof(double), hipMemcpyDefault, ctx->stream));
 
@@ -821,7 +854,8 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
                          P<double>(ctx->h64), precision == RFO_FP32 ? P<float>(ctx->h32) : nullptr,
                          P<int>(ctx->flags), ctx->stream));
   if (precision == RFO_BF16)
-    HIPCHK(rfo::launch_pack_bf16(P<double>(ctx->h64), ctx->hbf16.p, ctx->nnzb, ctx->stream));
+    HIPCHK(rfo::launch_pack_bf16(P<double>(ctx->h64), P<int32_t>(ctx->kc_src), ctx->n_chunks,
+                                 ctx->hbf16.p, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (*ctx->flags_h & 1) return fail(ctx, RFO_E_NUMERIC, "non-finite Hamiltonian values");

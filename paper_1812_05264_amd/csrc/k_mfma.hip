@@ -17,9 +17,12 @@
 // B operands come from that copy, half the bytes of the FP32 rows, and only
 // the nine real rows of X_J are loaded (lanes of rows 9..15 load nothing).
 //
-// A operands are pre-packed per block: entry g*9 + m (g < 3, m < 9) holds
-// H_hat[m][4g .. 4g+3] as four BF16 (zero where the column index exceeds 8);
-// lanes with m > 8 or g = 3 supply zeros without loading.
+// K is packed across the blocks of a block row: Y_I = [H_IJ1 H_IJ2 ...] [X_J1; X_J2; ...]
+// is one (9) x (9 nblk) times (9 nblk) x (probes) product, cut into chunks of 16
+// K rows, so that every K row of an MFMA is a real row of some X_J (only the last
+// chunk of a row has zero rows).  Per chunk, kc_idx lists the 16 gathered rows
+// J*9 + c and the A operands are pre-packed: entry g*9 + m (m < 9) holds the four
+// BF16 values H_hat_IJ[m][c] of K rows 4g .. 4g+3; lanes with m > 8 supply zeros.
 #include "device_util.h"
 #include "rfo_internal.h"
 
@@ -29,11 +32,16 @@ namespace {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
 
 }  // namespace
 
+// Occupancy 4 (at most 128 registers) is part of the design: the step is bound by
+// the gathers each wave keeps in flight, and at occupancy 3 the same kernel is
+// much slower.
 template <int NT, int U, bool NTH, int MODE>
-__global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_step9_bf16(
+    StepArgs a) {
   constexpr int TW = 16 * NT;  // probes per wave (tile width)
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -47,6 +55,7 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   unsigned short *outb = static_cast<unsigned short *>(a.outb);
   float *acc = static_cast<float *>(a.acc);
   const uint2 *hpack = static_cast<const uint2 *>(a.hval);
+  const i4 *kidx = reinterpret_cast<const i4 *>(a.kc_idx);
   const bool has_prev = a.c2 != 0.0;
   const bool add_r = a.beta != nullptr;
   const bool mom_on = a.part != nullptr;
@@ -122,29 +131,31 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
     const int64_t r0 = rg * a.rows_per_wg;
     const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
     for (int64_t I = r0 + wave; I < r1; I += kWaves) {
-      const int64_t beg = sld(a.row_ptr + I), end = sld(a.row_ptr + I + 1);
       f4 d[NT];
 #pragma unroll
       for (int t = 0; t < NT; ++t) d[t] = f4{0.f, 0.f, 0.f, 0.f};
-      for (int64_t nz0 = beg; nz0 < end; nz0 += U) {
+      const int64_t q0 = sld(a.kc_ptr + I), q1 = sld(a.kc_ptr + I + 1);
+      for (int64_t qc = q0; qc < q1; qc += U) {
         s4 av[U];
         VecN<unsigned short, NT> xr[U][4];
-        const bool a_live = g < 3 && n < 9;
+        const bool a_live = n < 9;
         const int a_idx = a_live ? g * 9 + n : 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          const int64_t nz = min(nz0 + u, end - 1);  // a repeated block is not accumulated
-          const int64_t J = sld(a.col + nz);
-          const uint2 p = hpack[nz * 27 + a_idx];
+          const int64_t q = min(qc + u, q1 - 1);  // a repeated chunk is not accumulated
+          const uint2 p = hpack[q * 36 + a_idx];
           av[u] = a_live ? s4{(short)(p.x & 0xffff), (short)(p.x >> 16), (short)(p.y & 0xffff),
                               (short)(p.y >> 16)}
                          : s4{0, 0, 0, 0};
-          // K rows 9..15 are zero: their lanes load nothing
+          // the chunk's 16 source rows (wave-uniform), four per lane group
+          const i4 k0 = sld(kidx + q * 4), k1 = sld(kidx + q * 4 + 1);
+          const i4 k2 = sld(kidx + q * 4 + 2), k3 = sld(kidx + q * 4 + 3);
+          const i4 kg = g == 0 ? k0 : (g == 1 ? k1 : (g == 2 ? k2 : k3));
+          const int src[4] = {kg.x, kg.y, kg.z, kg.w};
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
-            const int rr = 4 * g + kk;
-            if (rr < 9) {
-              xr[u][kk] = ldv<unsigned short, NT>(xb + (J * 9 + rr) * sp + cp);
+            if (src[kk] >= 0) {
+              xr[u][kk] = ldv<unsigned short, NT>(xb + (int64_t)src[kk] * sp + cp);
             } else {
 #pragma unroll
               for (int t = 0; t < NT; ++t) xr[u][kk].v[t] = 0;
@@ -153,7 +164,7 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-          if (nz0 + u < end) {
+          if (qc + u < q1) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
               const s4 bv = s4{(short)xr[u][0].v[t], (short)xr[u][1].v[t], (short)xr[u][2].v[t],
@@ -241,23 +252,24 @@ __global__ __launch_bounds__(kWG) void k_step9_bf16(StepArgs a) {
   }
 }
 
-// Pack H_hat (FP64 [nnzb][9][9]) into the A-operand layout above.
+// Pack H_hat (FP64 [nnzb][9][9]) into the chunked A-operand layout above.
 __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hhat,
-                                                   uint2 *__restrict__ hpack, int64_t nnzb) {
-  const int64_t total = nnzb * 27;
+                                                   const int32_t *__restrict__ kc_src,
+                                                   int64_t n_chunks, uint2 *__restrict__ apack) {
+  const int64_t total = n_chunks * 36;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t nz = e / 27;
-    const int r = (int)(e - nz * 27);
+    const int64_t q = e / 36;
+    const int r = (int)(e - q * 36);
     const int gg = r / 9, m = r - gg * 9;
     unsigned short v[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-      const int col = 4 * gg + kk;
-      const float f = col < 9 ? (float)hhat[nz * 81 + m * 9 + col] : 0.f;
+      const int code = kc_src[q * 16 + 4 * gg + kk];
+      const float f = code >= 0 ? (float)hhat[(int64_t)(code / 9) * 81 + m * 9 + code % 9] : 0.f;
       v[kk] = bf16_bits(f);
     }
-    hpack[e] = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
+    apack[e] = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
                           (unsigned)v[2] | ((unsigned)v[3] << 16));
   }
 }
@@ -274,11 +286,6 @@ const void *select_bf16(int nt_tiles, int u, int mode) {
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
   RFO_BF16_CASE(4, 4)
-  RFO_BF16_CASE(8, 1)
-  RFO_BF16_CASE(8, 2)
-  RFO_BF16_CASE(8, 4)
-  RFO_BF16_CASE(16, 1)
-  RFO_BF16_CASE(16, 2)
 #undef RFO_BF16_CASE
   return nullptr;
 }
@@ -300,12 +307,13 @@ hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s) {
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);
 }
 
-hipError_t launch_pack_bf16(const double *hhat, void *hpack, int64_t nnzb, hipStream_t s) {
-  int64_t blocks = (nnzb * 27 + kWG - 1) / kWG;
+hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks,
+                            void *apack, hipStream_t s) {
+  if (n_chunks == 0) return hipSuccess;
+  int64_t blocks = (n_chunks * 36 + kWG - 1) / kWG;
   if (blocks > 65536) blocks = 65536;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(kWG), 0, s, hhat,
-                     static_cast<uint2 *>(hpack), nnzb);
+  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(kWG), 0, s, hhat, kc_src, n_chunks,
+                     static_cast<uint2 *>(apack));
   return hipGetLastError();
 }
 

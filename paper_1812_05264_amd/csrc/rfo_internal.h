@@ -33,6 +33,8 @@ struct StepArgs {
   void *out;               // y_{k+1}
   const void *xb;          // BF16 steps: BF16 copy of y_k, the operand that is gathered
   void *outb;              // BF16 steps: BF16 copy of y_{k+1}, written with it
+  const int64_t *kc_ptr;   // BF16 steps: first K chunk of each block row [nb + 1]
+  const int32_t *kc_idx;   // BF16 steps: per chunk, the 16 gathered rows J*9 + c (-1: zero row)
   const uint64_t *sgn;     // [n][sp/64] sign bits (bit 1 = +1), or nullptr
   const double *rden;      // [n][sp] dense probes, or nullptr
   double c1, c2;
@@ -92,7 +94,11 @@ int step_blocks_per_cu(int bd, int precision, int ppl, int rpi);
 // ([nnzb + kStepPad][27] uint2), a.n_pt counts tiles of 16 * nt_tiles probes.
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s);
 int step_bf16_blocks_per_cu(int nt_tiles, int u);  // u = blocks per chunk (a.rpi)
-hipError_t launch_pack_bf16(const double *hhat, void *hpack, int64_t nnzb, hipStream_t s);
+// A operands of the K-packed BF16 step: chunk q, lane group g, output row m holds
+// H_hat[nz][m][c] for the four K rows 4g..4g+3 of the chunk, whose source codes
+// kc_src[16 q + k] = nz * 9 + c (-1: zero) list the block and column of each K row.
+hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks,
+                            void *apack, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Setup kernels
