@@ -17,8 +17,8 @@ Also reported on the same line:
   roofline      for the Chebyshev step kernel, from HIP events around its launches
   cpu_baseline  the FP64 oracle's Chebyshev steps on the host (bounded sample)
   energy_force  energy + gradient + Hellmann-Feynman forces on the 16,000-atom
-                Cu-like cluster (8000 terms, 256 probes), FP64 and FP32 with the
-                doubled moments (the library default), and FP64 with the direct
+                Cu-like cluster (8000 terms, 256 probes), FP64, FP32 and BF16 MFMA
+                with the doubled moments (the library default), and FP64 with the direct
                 recurrence, with the errors against the FP64 doubled result per atom;
                 and FP64 with a multi-color probe ensemble (one sample, coloring
                 radius 6 A) in place of the 256 Rademacher probes
@@ -409,7 +409,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="oracle Chebyshev steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--energy-force", type=int, default=1)
-    ap.add_argument("--ef-precisions", default="fp64,fp32")
+    ap.add_argument("--ef-precisions", default="fp64,fp32,bf16")
     ap.add_argument("--ef-direct", type=int, default=1,
                     help="also time FP64 energy_force with the direct recurrence (no doubling)")
     ap.add_argument("--ef-colored", type=float, default=6.0,
