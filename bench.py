@@ -270,7 +270,12 @@ def cluster_steps(args):
     from workloads.configs import CONFIGS, build_hamiltonian
     from workloads import rademacher
     out = {}
-    for name, precs in (("cu4k", ["fp64"]), ("cu16k", ["bf16", "fp32", "fp64"])):
+    runs = []
+    for item in args.cluster_configs.split(";"):
+        if item:
+            name, precs = item.split("=")
+            runs.append((name, precs.split(",")))
+    for name, precs in runs:
         cfg = CONFIGS[name]
         H, cl = build_hamiltonian(cfg)
         s = cfg.n_probes
@@ -284,7 +289,8 @@ def cluster_steps(args):
             torch.cuda.synchronize()
             eng.set_timing(True)
             t0 = time.perf_counter()
-            g = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=False)
+            n_terms = args.cluster_terms if args.cluster_terms > 0 else cfg.n_terms
+            g = eng.fermi_moments(cfg.T, cfg.mu, n_terms, moments=False)
             torch.cuda.synchronize()
             wall = time.perf_counter() - t0
             ms, n_steps = eng.step_timing()
@@ -309,7 +315,8 @@ def cluster_steps(args):
                     for k in ("N", "E", "F"):
                         r[f"d{k}_per_atom_vs_fp64"] = abs(r[k] - rows["fp64"][k]) / cl.n_atoms
         out[name] = {"atoms": cl.n_atoms, "orbitals": H.n, "nnzb": H.nnzb, "probes": s,
-                     "n_terms": cfg.n_terms, "T_eV": cfg.T, "mu_eV": cfg.mu, "runs": rows}
+                     "n_terms": args.cluster_terms if args.cluster_terms > 0 else cfg.n_terms,
+                     "T_eV": cfg.T, "mu_eV": cfg.mu, "runs": rows}
     return out
 
 
@@ -426,6 +433,12 @@ def main():
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
                     help="run only the energy_force leg (for profiling)")
+    ap.add_argument("--cluster-configs", default="cu4k=fp64;cu16k=bf16,fp32,fp64",
+                    help="cluster step legs: config=precisions, separated by ';'")
+    ap.add_argument("--cluster-terms", type=int, default=0,
+                    help="Chebyshev terms of the cluster step legs (0 = the configuration's)")
+    ap.add_argument("--only-cluster", action="store_true",
+                    help="run only the cluster step legs (for profiling)")
     ap.add_argument("--only-overlap", action="store_true",
                     help="run only the overlap leg")
     ap.add_argument("--only-rational", action="store_true",
@@ -461,6 +474,9 @@ def main():
         return
     if args.only_overlap:
         print(json.dumps({"overlap": overlap_leg(args)}))
+        return
+    if args.only_cluster:
+        print(json.dumps({"cluster_steps": cluster_steps(args)}))
         return
 
     import numpy as np
