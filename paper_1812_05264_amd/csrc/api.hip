@@ -39,6 +39,11 @@ struct rfo_ctx {
   std::vector<int32_t> col_h;
   DevBuf row_ptr, col, brow, tpos, hraw, h64, h32, hbf16, gscratch, nz_up, nz_low;
   int64_t n_up = 0, n_low = 0;
+  // BF16 9x9 steps: groups of consecutive upper blocks of one block row (at most
+  // kSddmmGroup blocks) for the segment gradient on the matrix cores
+  DevBuf up_grp;
+  int64_t n_up_grp = 0;
+  bool has_up_grp = false;
   // BF16 steps: K chunks of 16 rows per block row (first chunk of each row,
   // gathered row J*9 + c and source nz*9 + c of every K row)
   DevBuf kc_ptr, kc_idx, kc_src;
@@ -49,6 +54,7 @@ struct rfo_ctx {
   int64_t s = 0;
   int sp = 0;
   bool signs = false;
+  double w_uniform = 0.0;  // the common weight of the real probes, 0 if they differ
   DevBuf sgn, rden, w;
 
   // work buffers
@@ -79,7 +85,7 @@ struct rfo_ctx {
   ~rfo_ctx() {
     hipSetDevice(device);
     DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch, &nz_up, &nz_low,
-                     &kc_ptr, &kc_idx, &kc_src,
+                     &kc_ptr, &kc_idx, &kc_src, &up_grp,
                      &s64, &cg_part, &cg_sc, &GQ, &rat, &rat_part, &rat_sc, &rat_rho, &rat_coef,
                      &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
                      &costab, &small, &flags, &G, &dHdR, &forces};
@@ -262,6 +268,17 @@ void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
 }
 
 int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 : 1; }
+
+// The segment gradient of the BF16 steps runs on the matrix cores when every real
+// probe has the same weight (the weight is applied in FP64 after each step's
+// contraction).  FP32 steps keep the VALU contraction: an FP32-MFMA version
+// measured no faster at full size and sums in FP32.
+bool use_mfma_sddmm(const rfo_ctx *c) {
+  if (c->bd != 9 || c->prec != RFO_BF16 || c->w_uniform == 0.0 || !c->has_up_grp) return false;
+  if (c->sp % 32 != 0) return false;
+  if (const char *env = getenv("RFO_SDDMM_MFMA")) return atoi(env) != 0;
+  return true;
+}
 
 int sddmm_ppl(const rfo_ctx *c) {
   int ppl = (c->sp % 128 == 0) ? 2 : 1;
@@ -770,6 +787,7 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
       HIPCHK(hipMemcpyAsync(ctx->nz_low.p, low.data(), low.size() * sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream));
     ctx->n_up = (int64_t)up.size();
     ctx->n_low = (int64_t)low.size();
+
     HIPCHK(hipStreamSynchronize(ctx->stream));  // host vectors go out of scope
   }
   ctx->has_h = false;
@@ -860,6 +878,31 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (*ctx->flags_h & 1) return fail(ctx, RFO_E_NUMERIC, "non-finite Hamiltonian values");
   if (*ctx->flags_h & 2) return fail(ctx, RFO_E_INVALID, "Hamiltonian values are not symmetric (H_JI != H_IJ^T)");
+  ctx->has_up_grp = false;
+  if (block_dim == 9 && precision == RFO_BF16) {
+    // groups of the upper blocks (J >= I, in the order of the upper-block list)
+    const int gb = rfo::kSddmmGroup;
+    const std::vector<int64_t> &rp = ctx->row_ptr_h;
+    const std::vector<int32_t> &cl = ctx->col_h;
+    std::vector<int64_t> grp(1, 0);
+    int64_t q = 0;
+    for (int64_t I = 0; I < ctx->nb; ++I) {
+      int64_t in_row = 0;
+      for (int64_t z = rp[I]; z < rp[I + 1]; ++z) {
+        if ((int64_t)cl[z] < I) continue;
+        ++q;
+        if (++in_row % gb == 0) grp.push_back(q);
+      }
+      if (in_row % gb != 0) grp.push_back(q);
+    }
+    if (q != ctx->n_up) return fail(ctx, RFO_E_DEVICE, "internal: upper block count mismatch");
+    ctx->n_up_grp = (int64_t)grp.size() - 1;
+    TRY(ensure(ctx, ctx->up_grp, grp.size() * sizeof(int64_t)));
+    HIPCHK(hipMemcpyAsync(ctx->up_grp.p, grp.data(), grp.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                          ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));  // grp goes out of scope
+    ctx->has_up_grp = true;
+  }
   ctx->has_h = true;
   return RFO_OK;
 }
@@ -899,6 +942,9 @@ int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R, const double
                           n_probes * sizeof(double), n, hipMemcpyHostToDevice, ctx->stream));
   std::vector<double> w(sp, 0.0);
   for (int64_t c = 0; c < n_probes; ++c) w[c] = weights ? weights[c] : 1.0 / (double)n_probes;
+  ctx->w_uniform = w[0];
+  for (int64_t c = 1; c < n_probes; ++c)
+    if (w[c] != w[0]) ctx->w_uniform = 0.0;
   HIPCHK(hipMemcpyAsync(ctx->w.p, w.data(), sp * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipMemsetAsync(ctx->flags.p, 0, sizeof(int), ctx->stream));
   HIPCHK(rfo::launch_probe_pack(P<double>(ctx->rden), (int64_t)n, (int)n_probes, sp,
@@ -1151,7 +1197,33 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
     sd.nlist = ctx->n_up;
     sd.ppl = sddmm_ppl(ctx);
     sd.sym = 1;
-    HIPCHK(rfo::launch_sddmm(kp, sd, ctx->stream));
+    if (use_mfma_sddmm(ctx)) {
+      // the BF16 copies the BF16 steps gather, on the matrix cores
+      rfo::SddmmMfmaArgs sm;
+      memset(&sm, 0, sizeof(sm));
+      const size_t off = pl.vec_elems * sizeof(float);
+      sm.grp = P<int64_t>(ctx->up_grp);
+      sm.n_grp = ctx->n_up_grp;
+      sm.nzlist = sd.nzlist;
+      sm.brow = sd.brow;
+      sm.col = sd.col;
+      sm.sp = ctx->sp;
+      sm.s_real = (int)ctx->s;
+      sm.xbase = zs(0) + off;
+      sm.ybase = ys(0) + off;
+      sm.xstride = sm.ystride = (int64_t)(pl.slot_bytes / 2);
+      sm.count = sd.count;
+      sm.j0 = j0;
+      sm.scale = sd.scale;
+      sm.first = sd.first;
+      sm.rest = sd.rest;
+      sm.w0 = ctx->w_uniform;
+      sm.G = sd.G;
+      sm.accumulate = sd.accumulate;
+      HIPCHK(rfo::launch_sddmm_bf16(sm, ctx->stream));
+    } else {
+      HIPCHK(rfo::launch_sddmm(kp, sd, ctx->stream));
+    }
     if (q > 0) {
       // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}
       HIPCHK(hipMemcpyAsync(zs(m), zs(0), vb, hipMemcpyDeviceToDevice, ctx->stream));

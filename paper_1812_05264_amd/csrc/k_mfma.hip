@@ -252,6 +252,127 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   }
 }
 
+// ---------------------------------------------------------------------------
+// Segment gradient on the matrix cores (Analytical free-energy derivatives,
+// polynomial form: G_IJ accumulates z_{j+1,I} y_{j,J}^T over the steps and the
+// probes, here symmetrized), for the BF16 steps: it reads the BF16 copies of the
+// segment's vectors (the operands the steps gather).  For a block (I, J) the sum
+// over the probes c is a 9 x K by K x 9 contraction, K = the probes, on
+// v_mfma_f32_16x16x16_bf16: A = X_I (M = the 9 rows, padded to 16), B = Y_J^T
+// (N = the 9 rows of Y_J).  One wave owns a group of upper blocks of one block
+// row, so X_I and Y_I are loaded once for all of them; each block keeps a 16 x 16
+// FP32 tile (4 registers per lane), flushed into FP64 sums after every step t.
+// Lane l supplies A[l%16][4(l/16)..+3] and B[4(l/16)..+3][l%16] and holds
+// D[4(l/16)+i][l%16]; a lane loads 8 consecutive probes of a row with one
+// 16-byte access, the first four its K slots in one MFMA, the last four in the
+// next (the same probes in A and B).
+// ---------------------------------------------------------------------------
+template <int GB>
+__global__ __launch_bounds__(kWG) void k_sddmm_bf16(SddmmMfmaArgs a) {
+  constexpr int P = 8;  // probes per lane per load (16 bytes of BF16)
+  const int wave = uniform(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int64_t gi = (int64_t)xcd_logical(blockIdx.x, gridDim.x) * kWaves + wave;
+  if (gi >= a.n_grp) return;
+  const int64_t q0 = sld(a.grp + gi), q1 = sld(a.grp + gi + 1);
+  const int nb = (int)(q1 - q0);
+  const int m = lane & 15, kq = lane >> 4;
+  const bool live = m < 9;
+  int64_t nzs[GB], js[GB];
+#pragma unroll
+  for (int g = 0; g < GB; ++g) {
+    nzs[g] = sld(a.nzlist + (g < nb ? q0 + g : q0));
+    js[g] = sld(a.col + nzs[g]);
+  }
+  const int64_t I = sld(a.brow + nzs[0]);
+  const int sp = a.sp;
+  double acc[GB][4];
+#pragma unroll
+  for (int g = 0; g < GB; ++g)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[g][r] = 0.0;
+
+  for (int t = 0; t < a.count; ++t) {
+    f4 d[GB];
+#pragma unroll
+    for (int g = 0; g < GB; ++g) d[g] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int c0 = 0; c0 < sp; c0 += 4 * P) {
+      const int cp = c0 + kq * P;
+      // A operands X_I, Y_I (zero rows 9..15 and zero probes past s_real)
+      {
+        const unsigned short *X = static_cast<const unsigned short *>(a.xbase) + (int64_t)t * a.xstride;
+        const unsigned short *Y = static_cast<const unsigned short *>(a.ybase) + (int64_t)t * a.ystride;
+        VecN<unsigned short, 8> xa, ya;
+        if (live) {
+          xa = ldv<unsigned short, 8>(X + (I * 9 + m) * sp + cp);
+          ya = ldv<unsigned short, 8>(Y + (I * 9 + m) * sp + cp);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; ++e) xa.v[e] = ya.v[e] = 0;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (cp + e >= a.s_real) xa.v[e] = ya.v[e] = 0;
+        // the blocks of the group one at a time (loading all of them before the
+        // MFMAs needs occupancy 1 and measured slower)
+#pragma unroll
+        for (int g = 0; g < GB; ++g) {
+          if (g < nb) {
+            VecN<unsigned short, 8> yj, xj;
+            if (live) {
+              yj = ldv<unsigned short, 8>(Y + (js[g] * 9 + m) * sp + cp);
+              xj = ldv<unsigned short, 8>(X + (js[g] * 9 + m) * sp + cp);
+            } else {
+#pragma unroll
+              for (int e = 0; e < 8; ++e) yj.v[e] = xj.v[e] = 0;
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const s4 av = s4{(short)xa.v[4 * h], (short)xa.v[4 * h + 1], (short)xa.v[4 * h + 2],
+                               (short)xa.v[4 * h + 3]};
+              const s4 bv = s4{(short)yj.v[4 * h], (short)yj.v[4 * h + 1], (short)yj.v[4 * h + 2],
+                               (short)yj.v[4 * h + 3]};
+              const s4 av2 = s4{(short)ya.v[4 * h], (short)ya.v[4 * h + 1], (short)ya.v[4 * h + 2],
+                                (short)ya.v[4 * h + 3]};
+              const s4 bv2 = s4{(short)xj.v[4 * h], (short)xj.v[4 * h + 1], (short)xj.v[4 * h + 2],
+                                (short)xj.v[4 * h + 3]};
+              d[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, d[g], 0, 0, 0);
+              d[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av2, bv2, d[g], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    const double coef = a.scale * a.w0 * ((a.j0 + t == 0) ? a.first : a.rest);
+#pragma unroll
+    for (int g = 0; g < GB; ++g)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[g][r] = fma(coef, (double)d[g][r], acc[g][r]);
+  }
+  // lane holds G_IJ[4 kq + r][m] of every block of the group
+#pragma unroll
+  for (int g = 0; g < GB; ++g) {
+    if (g < nb) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * kq + r;
+        if (row < 9 && live) {
+          double *gp = a.G + nzs[g] * 81 + row * 9 + m;
+          *gp = a.accumulate ? *gp + acc[g][r] : acc[g][r];
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_sddmm_bf16(const SddmmMfmaArgs &a, hipStream_t s) {
+  if (a.n_grp == 0) return hipSuccess;
+  if (a.sp % 32 != 0) return hipErrorInvalidValue;  // 32 probes per load round of a wave
+  const dim3 grid((unsigned)((a.n_grp + kWaves - 1) / kWaves));
+  hipLaunchKernelGGL((k_sddmm_bf16<kSddmmGroup>), grid, dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
 // Pack H_hat (FP64 [nnzb][9][9]) into the chunked A-operand layout above.
 __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hhat,
                                                    const int32_t *__restrict__ kc_src,

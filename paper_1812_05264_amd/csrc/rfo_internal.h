@@ -161,6 +161,32 @@ struct SddmmArgs {
   int sym;                 // G[nz] (+)= sum_t coef_t sum_c w_c (X_I Y_J^T + Y_I X_J^T)
 };
 hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s);
+
+// Symmetric segment gradient of the BF16 steps on the matrix cores, from the
+// vectors' BF16 copies, with one weight w0 for the first s_real probes and zero
+// for the padding:
+//   G[nz] (+)= sum_t coef_t w0 sum_{c < s_real} (X_I Y_J^T + Y_I X_J^T)[:, c],
+// coef_t = scale * (j0 + t == 0 ? first : rest), for the upper blocks nzlist[q],
+// q in [grp[g], grp[g+1]): every group lies in one block row and holds at most
+// kSddmmGroup blocks.  The partial sums of one t (FP32 on the matrix cores) are
+// added in FP64.
+constexpr int kSddmmGroup = 6;  // measured best (10: 22% slower)
+struct SddmmMfmaArgs {
+  const int64_t *grp;      // [n_grp + 1]
+  int64_t n_grp;
+  const int64_t *nzlist;
+  const int64_t *brow;
+  const int32_t *col;
+  int sp, s_real;
+  const void *xbase, *ybase;  // BF16 (unsigned short) copies
+  int64_t xstride, ystride;   // elements between the vectors of consecutive t
+  int count;
+  int64_t j0;
+  double scale, first, rest, w0;
+  double *G;
+  int accumulate;
+};
+hipError_t launch_sddmm_bf16(const SddmmMfmaArgs &a, hipStream_t s);
 // G[nz] = G[tpos[nz]]^T for the listed blocks (completes a symmetric gradient).
 hipError_t launch_mirror(const int64_t *nzlist, int64_t nlist, const int64_t *tpos, int bd,
                          double *G, hipStream_t s);

@@ -98,3 +98,49 @@ def test_bf16_gradient_against_fp64():
     eG, eF = rel(g16["dFdH"], g64["dFdH"]), rel(f16, f64)
     print(f"bf16 gradient: dFdH {eG:.2e} forces {eF:.2e} F {abs(g16['F'] - g64['F']) / abs(g64['F']):.2e}")
     assert eG < 5e-2 and eF < 5e-2
+
+
+@pytest.mark.parametrize("s", [64, 200, 256])
+def test_bf16_segment_gradient_on_matrix_cores(s, monkeypatch):
+    """The segment gradient of BF16 steps runs on the matrix cores (from the
+    vectors' BF16 copies) when every probe has the same weight: against the VALU
+    contraction of the FP32 vectors of the same steps and against the FP64
+    oracle.  s = 200 leaves zero-weight padding inside the last probe chunk; block
+    rows with more than 6 upper blocks are split over several waves."""
+    banner(f"bf16 segment gradient on matrix cores s={s}")
+    cl = cu_cluster(201, config_id=27)
+    H = cl.bsr()
+    upper = np.bincount(H.block_rows()[H.col_idx >= H.block_rows()], minlength=H.n_block_rows)
+    assert upper.max() > 6
+    R = rademacher(H.n, s, config_id=603)
+    T, mu, p = 0.3, 0.4, 90
+    o = est.estimate(H, R, T, mu, p, gradient=True)
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H, precision="bf16")
+    eng.set_probes(R)
+    g = eng.energy_and_dEdH(T, mu, p)
+    monkeypatch.setenv("RFO_SDDMM_MFMA", "0")
+    v = eng.energy_and_dEdH(T, mu, p)
+    monkeypatch.delenv("RFO_SDDMM_MFMA")
+    assert g["F"] == v["F"]                               # the steps are the same
+    e_v, e_o = rel(g["dFdH"], v["dFdH"]), rel(g["dFdH"], o["dFdH"])
+    print(f"bf16 s={s}: matrix cores vs VALU {e_v:.2e}, vs oracle {e_o:.2e} "
+          f"(VALU vs oracle {rel(v['dFdH'], o['dFdH']):.2e})")
+    assert e_v < 1e-2 and e_o < 5e-2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16", 5e-2)])
+def test_segment_gradient_with_unequal_weights(prec, tol):
+    """Probes with different weights take the VALU contraction (the weight cannot
+    be applied after the matrix-core sums): against the weighted oracle."""
+    banner(f"segment gradient unequal weights {prec}")
+    cl = cu_cluster(55, config_id=28)
+    H = cl.bsr()
+    R = rademacher(H.n, 48, config_id=604)
+    w = np.random.default_rng(605).uniform(0.5, 1.5, size=48) / 48
+    o = est.estimate(H, R, 0.3, 0.2, 60, weights=w, gradient=True)
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H, precision=prec)
+    eng.set_probes(R, w)
+    g = eng.energy_and_dEdH(0.3, 0.2, 60)
+    assert rel(g["dFdH"], o["dFdH"]) < tol
