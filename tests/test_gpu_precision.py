@@ -144,3 +144,29 @@ def test_segment_gradient_with_unequal_weights(prec, tol):
     eng.set_probes(R, w)
     g = eng.energy_and_dEdH(0.3, 0.2, 60)
     assert rel(g["dFdH"], o["dFdH"]) < tol
+
+
+def test_kept_pattern_with_new_values_and_precisions():
+    """New values on the kept pattern (row_ptr and col_idx None) in BF16 and FP32 give
+    the same results as a fresh context with the full Hamiltonian; the BF16 K-chunk
+    tables and the gradient's block groups are rebuilt from the kept pattern."""
+    banner("kept pattern, new values, bf16 and fp32")
+    cl = cu_cluster(55, config_id=29)
+    H = cl.bsr()
+    H2 = H.with_values(H.values * 0.9)
+    R = rademacher(H.n, 64, config_id=606)
+    for prec in ("bf16", "fp32", "bf16"):
+        eng = engine_or_skip()
+        eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, prec)
+        eng.set_hamiltonian(None, None, H2.values, 9, H.e_min, H.e_max, prec)
+        eng.set_probes(R)
+        a = eng.fermi_moments(0.3, 0.2, 60, moments=True, density=True)
+        ga = eng.energy_and_dEdH(0.3, 0.2, 60)
+        fresh = engine_or_skip()
+        fresh.set_hamiltonian(H2.row_ptr, H2.col_idx, H2.values, 9, H.e_min, H.e_max, prec)
+        fresh.set_probes(R)
+        b = fresh.fermi_moments(0.3, 0.2, 60, moments=True, density=True)
+        gb = fresh.energy_and_dEdH(0.3, 0.2, 60)
+        assert np.array_equal(a["moments"], b["moments"]), prec
+        assert np.array_equal(a["density"], b["density"]), prec
+        assert np.array_equal(ga["dFdH"], gb["dFdH"]), prec
