@@ -116,3 +116,34 @@ def test_single_dense_probe():
     eng = engine_or_skip()
     load_hamiltonian(eng, H)
     check_all(eng, H, R, 0.25, 0.0, 33, weights=np.array([0.37]))
+
+
+@pytest.mark.parametrize("case", ["single_block", "diagonal_only", "one_probe"])
+def test_bf16_degenerate_inputs(case):
+    """BF16 MFMA steps (K chunks of one block, rows of one chunk) and the BF16
+    segment gradient on degenerate inputs against the FP64 path of the same
+    context: a single 9x9 block, a pattern without off-diagonal blocks, and one
+    probe column (63 zero-weight padding columns in the only probe tile)."""
+    banner(f"degenerate bf16 {case}")
+    if case == "single_block":
+        H, s = single_block(9, 810), 3
+    elif case == "diagonal_only":
+        H, s = diagonal_only(40, 9, 811), 64
+    else:
+        H, s = cu_cluster(13, config_id=812).bsr(), 1
+    R = rademacher(H.n, s, config_id=813)
+    eng = engine_or_skip()
+    out = {}
+    for prec in ("fp64", "bf16"):
+        eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, prec)
+        eng.set_probes(R)
+        g = eng.fermi_moments(0.3, 0.1, 24, moments=True, density=True)
+        e = eng.energy_and_dEdH(0.3, 0.1, 24)
+        out[prec] = (g, e)
+    (g64, e64), (g16, e16) = out["fp64"], out["bf16"]
+    assert np.all(np.isfinite(g16["moments"])) and np.all(np.isfinite(e16["dFdH"]))
+    assert rel(g16["moments"], g64["moments"]) < 3e-2
+    assert rel(g16["density"], g64["density"]) < 3e-2
+    assert abs(e16["F"] - e64["F"]) <= 1e-2 * max(1.0, abs(e64["F"]))
+    if np.any(e64["dFdH"]):
+        assert rel(e16["dFdH"], e64["dFdH"]) < 5e-2
