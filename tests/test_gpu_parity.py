@@ -220,3 +220,36 @@ def test_moments_bitwise_deterministic():
     assert np.array_equal(a["moments"], b["moments"])
     assert np.array_equal(a["density"], b["density"])
     assert a["N"] == b["N"] and a["E"] == b["E"] and a["F"] == b["F"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_gradient_segments_overlapped_equal_serial(prec, monkeypatch):
+    """The doubled adjoint can run each segment's gradient on a second stream while
+    the next segment replays on the first (two alternating sets of y, z slots; the
+    default for FP32): the result is bitwise the serial one, and the FP64 gradient
+    matches the oracle."""
+    banner(f"overlapped segments {prec}")
+    cl = cu_cluster(55, config_id=31)
+    H = cl.bsr()
+    R = rademacher(H.n, 64, config_id=607)
+    T, mu, p = 0.3, 0.2, 150             # 75 doubled steps: 9 segments of 9
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H, precision=prec)
+    eng.set_probes(R)
+    monkeypatch.setenv("RFO_OVERLAP", "1")
+    a = eng.energy_and_dEdH(T, mu, p)
+    fa = eng.hf_forces(cl.dH_dR())
+    monkeypatch.setenv("RFO_OVERLAP", "0")
+    b = eng.energy_and_dEdH(T, mu, p)
+    monkeypatch.setenv("RFO_OVERLAP", "1")
+    assert a["F"] == b["F"]
+    assert np.array_equal(a["dFdH"], b["dFdH"])
+    c = eng.energy_and_dEdH(T, mu, p)    # repeated overlapped call
+    monkeypatch.delenv("RFO_OVERLAP")
+    assert np.array_equal(a["dFdH"], c["dFdH"])
+    d = eng.energy_and_dEdH(T, mu, p)    # the precision's default schedule
+    assert np.array_equal(a["dFdH"], d["dFdH"])
+    if prec == "fp64":
+        o = est.estimate(H, R, T, mu, p, gradient=True)
+        assert rel(a["dFdH"], o["dFdH"]) < TOL
+        assert rel(fa, ofo.hf_forces(H, o["dFdH"], cl.dH_dR())) < TOL
