@@ -39,6 +39,20 @@
  *     block_dim is 1 or 9, every block row stores its diagonal block, the
  *     pattern is symmetric and H_JI = H_IJ^T.
  *   - Probe layout: R [n][s] row-major, n = n_block_rows * block_dim.
+ *   - Environment switches, read at each call, for measurement only: the defaults
+ *     are the measured best and results do not depend on them except where noted.
+ *       RFO_PPL          probes per lane of the step kernels (1, 2, 4)
+ *       RFO_RPI          1x1: rows per wave iteration (1, 2, 7); 9x9: blocks per chunk (1, 2)
+ *       RFO_ROWS_PER_WG  block rows per scheduling unit of the step kernels
+ *       RFO_GRID         resident workgroups of the step kernels (a multiple of 8)
+ *       RFO_BF16_U       BF16 steps: K chunks per iteration (1, 2, 4)
+ *       RFO_SDDMM_PPL    probes per lane of the VALU outer-product kernel (1, 2)
+ *       RFO_SDDMM_MFMA   0 keeps the BF16 segment gradient on the vector units
+ *                        (different rounding: the FP32 vectors instead of their BF16 copies)
+ *       RFO_OVERLAP      1 / 0 forces the overlapped / serial segment schedule of the
+ *                        doubled adjoint (default: overlapped for FP32; bitwise equal)
+ *       RFO_CPPL, RFO_CU, RFO_CGRID  probes per lane, rows or blocks per chunk and
+ *                        workgroups of the complex shifted product (rational estimate)
  */
 #ifndef RFO_H
 #define RFO_H
