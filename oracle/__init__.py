@@ -23,8 +23,9 @@ Three layers, each pinned separately by the CPU tests:
   overlap    the nonorthogonal-basis recurrence (H_hat S^{-1}) with exact sparse
              solves, P and Q blocks, and generalized-eigenvalue observables;
   rational   the rational (pole) expansion: a contour-integral pole fit of f and
-             g, the shifted solves (H - z_k) g_k = y by sparse LU, N, E, F,
-             density blocks and the rational free-energy derivative (S = I).
+             g, the shifted solves (H - z_k S) g_k = y by sparse LU, N, E, F,
+             the P (and with an overlap Q) blocks, and the rational free-energy
+             derivative (S = I).
 
 Also: the closed-form band of the periodic simple-cubic model and the
 Hellmann-Feynman force contraction (Observable response).
