@@ -89,6 +89,19 @@ def measured_traffic(name):
     return e.get("bytes_per_launch")
 
 
+def host_cpu():
+    """CPU model and logical CPU count of the host the CPU baseline ran on."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
+
+
 def cpu_baseline(H, R, n_steps):
     """The oracle's Chebyshev recurrence (scipy CSR x dense, single-threaded) on the host."""
     import numpy as np
@@ -557,7 +570,8 @@ def main():
                                 "cores": 1, "kind": "oracle",
                                 "sample": f"{n_sample} Chebyshev steps of the FP64 oracle (scipy CSR "
                                           f"x dense, single-threaded) on sc64 with all {s} probes; "
-                                          f"{dt:.1f} s"}
+                                          f"{dt:.1f} s",
+                                "host": host_cpu()}
     if args.energy_force:
         eng.close()
         del eng
