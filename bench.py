@@ -15,6 +15,7 @@ update (one update per three steps, plus one at the last step).
 
 Also reported on the same line:
   roofline      for the Chebyshev step kernel, from HIP events around its launches
+  sc64_fp32     the same call with FP32 steps: time and differences against FP64
   cpu_baseline  the FP64 oracle's Chebyshev steps on the host (bounded sample)
   energy_force  energy + gradient + Hellmann-Feynman forces on the 16,000-atom
                 Cu-like cluster (8000 terms, 256 probes), FP64, FP32 and BF16 MFMA
@@ -87,6 +88,39 @@ def measured_traffic(name):
     if not e or e.get("kernel_digest") != kernel_digest():
         return None
     return e.get("bytes_per_launch")
+
+
+def sc64_fp32(H, R, cfg, ref, dens64):
+    """The same sc64 call with FP32 vectors and H (FP64 moments, traces and
+    coefficients): step time, algorithmic rate and the differences of N, E, F per
+    site and of the density blocks against the FP64 call on the same probes."""
+    import numpy as np
+    import torch
+    import paper_1812_05264_amd as pkg
+    s, p = cfg.n_probes, cfg.n_terms
+    eng = pkg.Engine(0)
+    eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 1, H.e_min, H.e_max, "fp32")
+    eng.set_probes(R)
+    eng.fermi_moments(cfg.T, cfg.mu, p, moments=False, density=True)
+    torch.cuda.synchronize()
+    eng.set_timing(True)
+    g = eng.fermi_moments(cfg.T, cfg.mu, p, moments=False, density=True)
+    torch.cuda.synchronize()
+    step_ms, n_steps = eng.step_timing()
+    eng.set_timing(False)
+    eng.close()
+    b = step_bytes(H, s, 4, 4, density=True, p=p)
+    gbs = b / (step_ms * 1e-3) / 1e9
+    d64 = dens64.cpu().numpy()
+    out = {"kernel": "k_step1<float, float, 4, 7, 1, true, MODE>", "step_us": round(step_ms * 1e3, 2),
+           "bytes_per_hv_step": int(b), "GB_per_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+           "speedup_vs_fp64_step": None,
+           "density_rel_diff": float(np.linalg.norm(g["density"] - d64) / np.linalg.norm(d64))}
+    for k in ("N", "E", "F"):
+        out[f"d{k}_per_site_vs_fp64"] = abs(g[k] - ref[k]) / H.n
+    print(f"[bench] sc64 fp32: step {step_ms * 1e3:.1f} us, {gbs:.0f} GB/s, "
+          f"|dN|/site {out['dN_per_site_vs_fp64']:.1e}", flush=True)
+    return out
 
 
 def host_cpu():
@@ -446,6 +480,8 @@ def main():
                     help="Chebyshev terms of the energy_force leg (0 = the workload's 8000)")
     ap.add_argument("--only-energy-force", action="store_true",
                     help="run only the energy_force leg (for profiling)")
+    ap.add_argument("--sc64-fp32", type=int, default=1,
+                    help="also time sc64 with FP32 steps and report its differences (0 = skip)")
     ap.add_argument("--cluster-configs", default="cu4k=fp64;cu16k=bf16,fp32,fp64",
                     help="cluster step legs: config=precisions, separated by ';'")
     ap.add_argument("--cluster-terms", type=int, default=0,
@@ -572,6 +608,9 @@ def main():
                                           f"x dense, single-threaded) on sc64 with all {s} probes; "
                                           f"{dt:.1f} s",
                                 "host": host_cpu()}
+    if args.sc64_fp32 and args.precision == "fp64":
+        line["sc64_fp32"] = sc64_fp32(H, R, cfg, last, dens)
+        line["sc64_fp32"]["speedup_vs_fp64_step"] = round(step_ms / (line["sc64_fp32"]["step_us"] * 1e-3), 3)
     if args.energy_force:
         eng.close()
         del eng
