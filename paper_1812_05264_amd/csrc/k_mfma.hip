@@ -184,7 +184,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int64_t row = I * 9 + min(4 * g + i, 8);
         if (has_prev) pv4[slot] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
                                       : ldv<float, NT>(prev + row * sp + cp);
-        if (m >= 2 || DBL) xs4[slot] = ldv<float, NT>(x + row * sp + cp);
+        // the row's own FP32 y_k is read once: non-temporal, so that it does not
+        // displace the gathered BF16 copies (measured 4% faster)
+        if (m >= 2 || DBL) xs4[slot] = ldv_nt<float, NT>(x + row * sp + cp);
         if (need_r && a.sgn) sw4[slot] = a.sgn[row * nw + (cp >> 6)];
       };
       if constexpr (NPRE == 4) {
