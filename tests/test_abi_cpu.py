@@ -41,3 +41,26 @@ def test_create_without_device_reports_error(gpu_available):
     with pytest.raises(pkg.RfoError) as ei:
         pkg.Engine()
     assert ei.value.status in ("RFO_E_DEVICE", "RFO_E_INVALID")
+
+
+def test_library_exports_no_other_c_symbols():
+    """Every exported symbol with C linkage (not a mangled C++ name) is one the
+    header declares: internal functions do not leak into the ABI."""
+    import shutil
+    import subprocess
+    pkg = pytest.importorskip("paper_1812_05264_amd")
+    path = pkg.library_path()
+    if not os.path.exists(path):
+        pytest.fail(f"{path} not built: run python -m paper_1812_05264_amd.build")
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm not available")
+    out = subprocess.run([nm, "-D", "--defined-only", path], stdout=subprocess.PIPE, text=True,
+                         check=True).stdout
+    exported = set()
+    for line in out.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[1] in ("T", "W"):
+            exported.add(parts[2])
+    c_names = {n for n in exported if not n.startswith("_Z")}
+    assert c_names == set(declared_symbols()), sorted(c_names ^ set(declared_symbols()))
