@@ -63,6 +63,11 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden symbols by default; these are its exports. */
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
+
 typedef struct rfo_ctx rfo_ctx;
 
 typedef enum {
@@ -275,6 +280,10 @@ int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
  * last reset, and their count. */
 int rfo_set_timing(rfo_ctx *ctx, int enabled);
 int rfo_step_timing(rfo_ctx *ctx, double *mean_ms, int64_t *n_steps);
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

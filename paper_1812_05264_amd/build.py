@@ -22,8 +22,9 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# host symbols are hidden unless declared in include/rfo.h (the C ABI)
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
-          "-Wno-unused-command-line-argument"]
+          "-Wno-unused-command-line-argument", "-Xarch_host", "-fvisibility=hidden"]
 
 
 def _run(cmd):

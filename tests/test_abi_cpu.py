@@ -43,9 +43,10 @@ def test_create_without_device_reports_error(gpu_available):
     assert ei.value.status in ("RFO_E_DEVICE", "RFO_E_INVALID")
 
 
-def test_library_exports_no_other_c_symbols():
-    """Every exported symbol with C linkage (not a mangled C++ name) is one the
-    header declares: internal functions do not leak into the ABI."""
+def test_library_exports_no_other_functions():
+    """The exported functions are exactly the ones the header declares: internal C
+    and C++ functions are hidden (only the HIP runtime's kernel handles, which are
+    data symbols, are exported besides them)."""
     import shutil
     import subprocess
     pkg = pytest.importorskip("paper_1812_05264_amd")
@@ -57,10 +58,9 @@ def test_library_exports_no_other_c_symbols():
         pytest.skip("nm not available")
     out = subprocess.run([nm, "-D", "--defined-only", path], stdout=subprocess.PIPE, text=True,
                          check=True).stdout
-    exported = set()
+    functions = set()
     for line in out.splitlines():
         parts = line.split()
-        if len(parts) == 3 and parts[1] in ("T", "W"):
-            exported.add(parts[2])
-    c_names = {n for n in exported if not n.startswith("_Z")}
-    assert c_names == set(declared_symbols()), sorted(c_names ^ set(declared_symbols()))
+        if len(parts) == 3 and parts[1] in ("T", "W", "i"):
+            functions.add(parts[2])
+    assert functions == set(declared_symbols()), sorted(functions ^ set(declared_symbols()))
