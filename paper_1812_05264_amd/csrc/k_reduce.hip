@@ -10,7 +10,9 @@
 //
 // One wave owns one block: lanes run along the contraction index (probes), each
 // lane keeps all bd*bd partial sums in registers over the whole contraction, and
-// a fixed butterfly reduces them at the end (bitwise reproducible).  Workgroups
+// a fixed butterfly reduces them at the end (bitwise reproducible).  The gradient's
+// two outer products (X_I Y_J^T and Y_I X_J^T) load their rows one after the
+// other, so that only one pair of row sets is live and two waves fit per SIMD.  Workgroups
 // are remapped so that each XCD takes one contiguous range of the block list:
 // the waves in flight on an XCD then read the vectors of a narrow band of block
 // rows, which that XCD's L2 holds.
@@ -20,7 +22,7 @@
 namespace rfo {
 
 template <int BD, typename VT, int PPL, bool SYM>
-__global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k_sddmm(SddmmArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int64_t widx = (int64_t)xcd_logical(blockIdx.x, gridDim.x) * kWaves + wave;
@@ -41,42 +43,49 @@ __global__ __launch_bounds__(kWG) void k_sddmm(SddmmArgs a) {
     const VT *X = static_cast<const VT *>(a.xbase) + (int64_t)t * a.xstride;
     const VT *Y = a.ybase ? static_cast<const VT *>(a.ybase) + (int64_t)t * a.ystride : nullptr;
     for (int c = lane * PPL; c < sp; c += 64 * PPL) {
-      VecN<VT, PPL> xv[BD], yv[BD];
-      VecN<VT, PPL> xj[SYM ? BD : 1], yi[SYM ? BD : 1];
+      double wc[PPL];
 #pragma unroll
-      for (int i = 0; i < BD; ++i) xv[i] = ldv<VT, PPL>(X + (I * BD + i) * sp + c);
-      if constexpr (SYM) {
+      for (int q = 0; q < PPL; ++q) wc[q] = a.w[c + q] * coef;
+      // phase 1: X_I Y_J^T (Y from the probes when there is no Y vector)
+      {
+        VecN<VT, PPL> xv[BD], yv[BD];
 #pragma unroll
-        for (int i = 0; i < BD; ++i) {
-          xj[i] = ldv<VT, PPL>(X + (J * BD + i) * sp + c);
-          yi[i] = ldv<VT, PPL>(Y + (I * BD + i) * sp + c);
+        for (int i = 0; i < BD; ++i) xv[i] = ldv<VT, PPL>(X + (I * BD + i) * sp + c);
+        if (Y) {
+#pragma unroll
+          for (int j = 0; j < BD; ++j) yv[j] = ldv<VT, PPL>(Y + (J * BD + j) * sp + c);
+        } else {
+#pragma unroll
+          for (int j = 0; j < BD; ++j)
+#pragma unroll
+            for (int q = 0; q < PPL; ++q)
+              yv[j].v[q] = (VT)probe_value(a.sgn, a.rden, J * BD + j, sp, c + q);
+        }
+#pragma unroll
+        for (int q = 0; q < PPL; ++q) {
+          double xa[BD];
+#pragma unroll
+          for (int i = 0; i < BD; ++i) xa[i] = wc[q] * (double)xv[i].v[q];
+#pragma unroll
+          for (int i = 0; i < BD; ++i)
+#pragma unroll
+            for (int j = 0; j < BD; ++j) s[i][j] = fma(xa[i], (double)yv[j].v[q], s[i][j]);
         }
       }
-      if (Y) {
+      if constexpr (SYM) {
+        // phase 2: + Y_I X_J^T, its rows requested only after phase 1's products
+        __builtin_amdgcn_sched_barrier(0);
+        VecN<VT, PPL> xj[BD], yi[BD];
 #pragma unroll
-        for (int j = 0; j < BD; ++j) yv[j] = ldv<VT, PPL>(Y + (J * BD + j) * sp + c);
-      } else {
+        for (int i = 0; i < BD; ++i) {
+          yi[i] = ldv<VT, PPL>(Y + (I * BD + i) * sp + c);
+          xj[i] = ldv<VT, PPL>(X + (J * BD + i) * sp + c);
+        }
 #pragma unroll
-        for (int j = 0; j < BD; ++j)
-#pragma unroll
-          for (int q = 0; q < PPL; ++q)
-            yv[j].v[q] = (VT)probe_value(a.sgn, a.rden, J * BD + j, sp, c + q);
-      }
-#pragma unroll
-      for (int q = 0; q < PPL; ++q) {
-        const double wc = a.w[c + q] * coef;
-        double xa[BD];
-#pragma unroll
-        for (int i = 0; i < BD; ++i) xa[i] = wc * (double)xv[i].v[q];
-#pragma unroll
-        for (int i = 0; i < BD; ++i)
-#pragma unroll
-          for (int j = 0; j < BD; ++j) s[i][j] = fma(xa[i], (double)yv[j].v[q], s[i][j]);
-        if constexpr (SYM) {
-          // + Y_I X_J^T: the symmetric part of the raw outer products
+        for (int q = 0; q < PPL; ++q) {
           double ya[BD];
 #pragma unroll
-          for (int i = 0; i < BD; ++i) ya[i] = wc * (double)yi[i].v[q];
+          for (int i = 0; i < BD; ++i) ya[i] = wc[q] * (double)yi[i].v[q];
 #pragma unroll
           for (int i = 0; i < BD; ++i)
 #pragma unroll
