@@ -49,6 +49,10 @@
  *       RFO_SDDMM_PPL    probes per lane of the VALU outer-product kernel (1, 2)
  *       RFO_SDDMM_MFMA   0 keeps the BF16 segment gradient on the vector units
  *                        (different rounding: the FP32 vectors instead of their BF16 copies)
+ *       RFO_SDDMM_TG     steps per launch of the segment gradient on the vector units
+ *                        (default 32; 0 = one launch per segment); RFO_SDDMM_TG_BF16 the
+ *                        same for the matrix-core gradient (default 8).  The gradient is
+ *                        summed per launch, so its rounding depends on them.
  *       RFO_OVERLAP      1 / 0 forces the overlapped / serial segment schedule of the
  *                        doubled adjoint (default: overlapped for FP32; bitwise equal)
  *       RFO_CPPL, RFO_CU, RFO_CGRID  probes per lane, rows or blocks per chunk and

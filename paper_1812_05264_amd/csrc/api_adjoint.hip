@@ -206,9 +206,9 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
       sm.w0 = ctx->w_uniform;
       sm.G = sd.G;
       sm.accumulate = sd.accumulate;
-      HIPCHK(rfo::launch_sddmm_bf16(sm, sd_stream));
+      HIPCHK(launch_sddmm_bf16_segment(sm, pl.slot_bytes, sd_stream));
     } else {
-      HIPCHK(rfo::launch_sddmm(kp, sd, sd_stream));
+      HIPCHK(launch_sddmm_segment(kp, sd, pl.slot_bytes, sd_stream));
     }
     if (overlap) {
       HIPCHK(hipEventRecord(ctx->ev_sd[cur], ctx->side));
@@ -371,7 +371,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       a.nzlist = P<int64_t>(ctx->nz_up);
       a.nlist = ctx->n_up;
       a.ppl = sddmm_ppl(ctx);
-      HIPCHK(rfo::launch_sddmm(kp, a, ctx->stream));
+      HIPCHK(launch_sddmm_segment(kp, a, pl.slot_bytes, ctx->stream));
       if (q > 0) {
         // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}
         HIPCHK(hipMemcpyAsync(zs(m), zs(0), vb, hipMemcpyDeviceToDevice, ctx->stream));

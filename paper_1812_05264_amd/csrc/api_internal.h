@@ -288,6 +288,52 @@ inline bool use_mfma_sddmm(const rfo_ctx *c) {
   return true;
 }
 
+// The segment gradient in launches of at most sddmm_steps() steps each (8 for
+// the BF16 kernel): all resident waves then work on the same few steps, so the
+// rows of X_t and Y_t that the blocks of a band of block rows share are read
+// while the L2 holds them.  Measured on the 16,000-atom cluster at 8000 terms
+// (segments of 64 steps).
+inline int sddmm_steps() {
+  int tg = 32;
+  if (const char *env = getenv("RFO_SDDMM_TG")) tg = atoi(env);
+  return tg;
+}
+
+inline hipError_t launch_sddmm_segment(int precision, const rfo::SddmmArgs &a, size_t slot_bytes,
+                                       hipStream_t s) {
+  const int tg = sddmm_steps();
+  if (tg <= 0 || a.count <= tg) return rfo::launch_sddmm(precision, a, s);
+  rfo::SddmmArgs b = a;
+  for (int t0 = 0; t0 < a.count; t0 += tg) {
+    b.xbase = static_cast<const char *>(a.xbase) + (size_t)t0 * slot_bytes;
+    b.ybase = static_cast<const char *>(a.ybase) + (size_t)t0 * slot_bytes;
+    b.count = std::min(tg, a.count - t0);
+    b.j0 = a.j0 + t0;
+    b.accumulate = t0 == 0 ? a.accumulate : 1;
+    const hipError_t e = rfo::launch_sddmm(precision, b, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+inline hipError_t launch_sddmm_bf16_segment(const rfo::SddmmMfmaArgs &a, size_t slot_bytes,
+                                            hipStream_t s) {
+  int tg = 8;
+  if (const char *env = getenv("RFO_SDDMM_TG_BF16")) tg = atoi(env);
+  if (tg <= 0 || a.count <= tg) return rfo::launch_sddmm_bf16(a, s);
+  rfo::SddmmMfmaArgs b = a;
+  for (int t0 = 0; t0 < a.count; t0 += tg) {
+    b.xbase = static_cast<const char *>(a.xbase) + (size_t)t0 * slot_bytes;
+    b.ybase = static_cast<const char *>(a.ybase) + (size_t)t0 * slot_bytes;
+    b.count = std::min(tg, a.count - t0);
+    b.j0 = a.j0 + t0;
+    b.accumulate = t0 == 0 ? a.accumulate : 1;
+    const hipError_t e = rfo::launch_sddmm_bf16(b, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 inline int sddmm_ppl(const rfo_ctx *c) {
   int ppl = (c->sp % 128 == 0) ? 2 : 1;
   if (const char *env = getenv("RFO_SDDMM_PPL")) ppl = atoi(env) == 2 && c->sp % 128 == 0 ? 2 : 1;

@@ -253,3 +253,36 @@ def test_gradient_segments_overlapped_equal_serial(prec, monkeypatch):
         o = est.estimate(H, R, T, mu, p, gradient=True)
         assert rel(a["dFdH"], o["dFdH"]) < TOL
         assert rel(fa, ofo.hf_forces(H, o["dFdH"], cl.dH_dR())) < TOL
+
+
+@pytest.mark.parametrize("prec,doubling", [("fp64", True), ("fp64", False), ("fp32", True),
+                                           ("bf16", True)])
+def test_gradient_segments_in_step_groups(prec, doubling, monkeypatch):
+    """Each segment's gradient runs in launches of a few steps (the per-launch sums
+    are added to G in step order): against one launch per segment the result
+    differs only by FP64 rounding, F is unchanged, and in FP64 both match the
+    oracle."""
+    banner(f"segment gradient in step groups {prec} doubling={doubling}")
+    cl = cu_cluster(55, config_id=32)
+    H = cl.bsr()
+    R = rademacher(H.n, 64, config_id=608)
+    T, mu, p = 0.3, 0.2, 150             # segments of 9 (doubled) or 12 (direct) steps
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H, precision=prec)
+    eng.set_probes(R)
+    eng.set_moment_doubling(doubling)
+    monkeypatch.setenv("RFO_SDDMM_TG", "0")
+    monkeypatch.setenv("RFO_SDDMM_TG_BF16", "0")
+    whole = eng.energy_and_dEdH(T, mu, p)
+    for tg in ("1", "2", "5"):
+        monkeypatch.setenv("RFO_SDDMM_TG", tg)
+        monkeypatch.setenv("RFO_SDDMM_TG_BF16", tg)
+        g = eng.energy_and_dEdH(T, mu, p)
+        assert g["F"] == whole["F"], tg
+        e = rel(g["dFdH"], whole["dFdH"])
+        print(f"{prec} tg={tg}: {e:.2e} from one launch per segment")
+        assert e < 1e-12, tg
+    if prec == "fp64":
+        o = est.estimate(H, R, T, mu, p, gradient=True)
+        assert rel(whole["dFdH"], o["dFdH"]) < TOL
+        assert rel(g["dFdH"], o["dFdH"]) < TOL
