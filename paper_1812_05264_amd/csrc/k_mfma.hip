@@ -267,10 +267,11 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // Lane l supplies A[l%16][4(l/16)..+3] and B[4(l/16)..+3][l%16] and holds
 // D[4(l/16)+i][l%16]; a lane loads 8 consecutive probes of a row with one
 // 16-byte access, the first four its K slots in one MFMA, the last four in the
-// next (the same probes in A and B).
+// next (the same probes in A and B).  Four waves per SIMD requested from the
+// compiler (125 VGPRs, no spills; the default took 150 and three waves).
 // ---------------------------------------------------------------------------
 template <int GB>
-__global__ __launch_bounds__(kWG) void k_sddmm_bf16(SddmmMfmaArgs a) {
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_sddmm_bf16(SddmmMfmaArgs a) {
   constexpr int P = 8;  // probes per lane per load (16 bytes of BF16)
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
