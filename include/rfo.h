@@ -54,7 +54,7 @@
  *                        same for the matrix-core gradient (default 8).  The gradient is
  *                        summed per launch, so its rounding depends on them.
  *       RFO_OVERLAP      1 / 0 forces the overlapped / serial segment schedule of the
- *                        doubled adjoint (default: overlapped for FP32; bitwise equal)
+ *                        doubled adjoint (default: serial; bitwise equal)
  *       RFO_CPPL, RFO_CU, RFO_CGRID  probes per lane, rows or blocks per chunk and
  *                        workgroups of the complex shifted product (rational estimate)
  */

@@ -25,10 +25,11 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   const int64_t Q = (K + m - 1) / m;
   // with more than one segment, segment q's gradient can run on the side stream while
   // segment q - 1 replays and reverses on the main stream, the segments alternating
-  // between two sets of y and z slots.  Measured on cu16k: FP32 5.62 against 5.80 s,
-  // FP64 10.05 against 9.56 s (the persistent step kernels lose the CUs the gradient
-  // holds), BF16 unchanged; so it is the default for FP32 only.
-  bool overlap = Q > 1 && ctx->prec == RFO_FP32;
+  // between two sets of y and z slots.  Measured on cu16k with the gradient kernels in
+  // step-group launches: FP64 10.05 against 9.29 s, FP32 5.63 against 5.46 s, BF16
+  // 4.04 against 3.96 s (the persistent step kernels lose the CUs the gradient holds),
+  // so the serial schedule is the default and the overlap is taken on request.
+  bool overlap = false;
   if (const char *env = getenv("RFO_OVERLAP")) overlap = Q > 1 && atoi(env) != 0;
   const int n_sets = overlap ? 2 : 1;
   // vector slots: n_sets x (ys [m + 2] | zs [m + 2]) | checkpoints [2 (Q - 1)]

@@ -225,9 +225,9 @@ def test_moments_bitwise_deterministic():
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_gradient_segments_overlapped_equal_serial(prec, monkeypatch):
     """The doubled adjoint can run each segment's gradient on a second stream while
-    the next segment replays on the first (two alternating sets of y, z slots; the
-    default for FP32): the result is bitwise the serial one, and the FP64 gradient
-    matches the oracle."""
+    the next segment replays on the first (two alternating sets of y, z slots, on
+    request): the result is bitwise the serial one, and the FP64 gradient matches
+    the oracle."""
     banner(f"overlapped segments {prec}")
     cl = cu_cluster(55, config_id=31)
     H = cl.bsr()
