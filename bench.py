@@ -17,12 +17,18 @@ Also reported on the same line:
   roofline      for the Chebyshev step kernel, from HIP events around its launches
   sc64_fp32     the same call with FP32 steps: time and differences against FP64
   cpu_baseline  the FP64 oracle's Chebyshev steps on the host (bounded sample)
+A "step" of the line (steps, ms_per_step) is one fermi_moments call, i.e. one pass of
+the whole hot path; each holds chebyshev_steps_per_step = 2047 Chebyshev steps, whose
+mean kernel time is roofline.mean_launch_us.
+
   energy_force  energy + gradient + Hellmann-Feynman forces on the 16,000-atom
                 Cu-like cluster (8000 terms, 256 probes), FP64, FP32 and BF16 MFMA
                 with the doubled moments (the library default), and FP64 with the direct
                 recurrence, with the errors against the FP64 doubled result per atom;
                 and FP64 with a multi-color probe ensemble (one sample, coloring
-                radius 6 A) in place of the 256 Rademacher probes
+                radius 6 A) in place of the 256 Rademacher probes; oracle_gate: per
+                precision, E, F, gradient blocks and forces of the oracle fixtures' two
+                probes against the FP64 oracle (the 1e-6 eV/atom gate)
   overlap       the nonorthogonal basis (S^-1 by conjugate gradients in every step)
                 on the 4,000-atom cluster, 200 terms, moments and P, Q blocks
   cluster_steps Chebyshev step throughput on the Cu-like clusters: cu4k in FP64 (4,000
@@ -149,6 +155,62 @@ def cpu_baseline(H, R, n_steps):
     return dt
 
 
+def oracle_gate(H, cl, cfg, n_terms, precs):
+    """The energy+force accuracy gate against the FP64 oracle on its probe subset: the two
+    probes of the committed oracle fixtures (tests/golden/oracle_cu16k_grad16.json for the
+    per-probe E and F, oracle_cu16k_grad_G.json for the gradient blocks of the 32
+    finite-difference atoms' block rows, their forces and F), as a two-probe estimate with
+    weights 1/2, in each precision: |F - F_oracle| and |E - E_oracle| per atom, the worst
+    per-block relative error of G on those rows, and the force errors on those atoms.
+    Returns None when the fixtures are missing or were made for another input."""
+    import numpy as np
+    import paper_1812_05264_amd as pkg
+    from workloads import rademacher
+    gold = os.path.join(ROOT, "tests", "golden")
+    try:
+        fe = json.load(open(os.path.join(gold, "oracle_cu16k_grad16.json")))
+        fg = json.load(open(os.path.join(gold, "oracle_cu16k_grad_G.json")))
+    except (OSError, ValueError):
+        return None
+    digest = H.digest()
+    if (fe["input_digest"] != digest or fg["input_digest"] != digest or fe["columns"] != fg["columns"]
+            or fe["n_terms"] != n_terms or fg["n_terms"] != n_terms):
+        return None
+    R2 = rademacher(H.n, fe["n_probes_drawn"], config_id=cfg.config_id)[:, fe["columns"]]
+    w2 = np.full(R2.shape[1], 1.0 / R2.shape[1])
+    scale = w2[0] / fg["weights"][0]
+    nz = np.asarray(fg["nz"], dtype=np.int64)
+    G_want = scale * np.asarray(fg["G"]).reshape(-1, 9, 9)
+    f_want = scale * np.asarray(fg["forces"])
+    atoms = np.asarray(fg["atoms"], dtype=np.int64)
+    F_want = float(np.dot(w2, fe["F_c"]))
+    E_want = float(np.dot(w2, fe["E_c"]))
+    D = cl.dH_dR()
+    out = {"probes": "the oracle fixtures' two Rademacher probes, weights 1/2",
+           "F_oracle_eV": F_want, "E_oracle_eV": E_want}
+    for prec in precs:
+        eng = pkg.Engine(0)
+        eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, prec)
+        eng.set_probes(R2, w2)
+        g = eng.energy_and_dEdH(cfg.T, cfg.mu, n_terms)
+        f = eng.hf_forces(D)[atoms]
+        eng.close()
+        del eng
+        Gd = np.max(np.abs(g["dFdH"][nz] - G_want).reshape(nz.size, -1), axis=1)
+        Gs = np.max(np.abs(G_want).reshape(nz.size, -1), axis=1)
+        r = {"dF_eV_per_atom": abs(g["F"] - F_want) / cl.n_atoms,
+             "dE_eV_per_atom": abs(g["E"] - E_want) / cl.n_atoms,
+             "G_rows_worst_block_rel_err": float(np.max(Gd / Gs)),
+             "force_max_err_eV_per_A": float(np.max(np.abs(f - f_want))),
+             "force_rms_err_eV_per_A": float(np.sqrt(np.mean((f - f_want) ** 2)))}
+        r["within_1e-6_eV_per_atom"] = bool(r["dF_eV_per_atom"] <= 1e-6 and r["dE_eV_per_atom"] <= 1e-6)
+        out[prec] = r
+        print(f"[bench] oracle gate {prec}: dF {r['dF_eV_per_atom']:.2e} dE {r['dE_eV_per_atom']:.2e} "
+              f"eV/atom, G rows {r['G_rows_worst_block_rel_err']:.2e}, force max "
+              f"{r['force_max_err_eV_per_A']:.2e} eV/A", flush=True)
+    return out
+
+
 def energy_force(args):
     import numpy as np
     import paper_1812_05264_amd as pkg
@@ -207,6 +269,8 @@ def energy_force(args):
             out["colored"]["dF_eV_per_atom_vs_rademacher"] = abs(g["F"] - g64["F"]) / cl.n_atoms
             out["colored"]["force_rms_vs_rademacher_eV_per_A"] = float(np.sqrt(np.mean((f - f64) ** 2)))
         print(f"[bench] energy_force colored r={args.ef_colored} ({Rc.shape[1]} columns): {dt:.3f} s", flush=True)
+    if args.ef_gate and n_terms == cfg.n_terms:
+        out["oracle_gate"] = oracle_gate(H, cl, cfg, n_terms, args.ef_precisions.split(","))
     if "fp64" in res:
         _, g64, f64 = res["fp64"]
         for prec, (dt, g, f) in res.items():
@@ -466,6 +530,8 @@ def main():
     ap.add_argument("--ef-precisions", default="fp64,fp32,bf16")
     ap.add_argument("--ef-direct", type=int, default=1,
                     help="also time FP64 energy_force with the direct recurrence (no doubling)")
+    ap.add_argument("--ef-gate", type=int, default=1,
+                    help="energy_force: errors against the FP64 oracle fixtures per precision (0 = skip)")
     ap.add_argument("--ef-colored", type=float, default=6.0,
                     help="coloring radius (A) of a multi-color probe energy_force run (0 = skip)")
     ap.add_argument("--ov-terms", type=int, default=200,
@@ -579,6 +645,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "chebyshev_steps_per_step": p - 1,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

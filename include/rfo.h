@@ -39,24 +39,8 @@
  *     block_dim is 1 or 9, every block row stores its diagonal block, the
  *     pattern is symmetric and H_JI = H_IJ^T.
  *   - Probe layout: R [n][s] row-major, n = n_block_rows * block_dim.
- *   - Environment switches, read at each call, for measurement only: the defaults
- *     are the measured best and results do not depend on them except where noted.
- *       RFO_PPL          probes per lane of the step kernels (1, 2, 4)
- *       RFO_RPI          1x1: rows per wave iteration (1, 2, 7); 9x9: blocks per chunk (1, 2)
- *       RFO_ROWS_PER_WG  block rows per scheduling unit of the step kernels
- *       RFO_GRID         resident workgroups of the step kernels (a multiple of 8)
- *       RFO_BF16_U       BF16 steps: K chunks per iteration (1, 2, 4)
- *       RFO_SDDMM_PPL    probes per lane of the VALU outer-product kernel (1, 2)
- *       RFO_SDDMM_MFMA   0 keeps the BF16 segment gradient on the vector units
- *                        (different rounding: the FP32 vectors instead of their BF16 copies)
- *       RFO_SDDMM_TG     steps per launch of the segment gradient on the vector units
- *                        (default 32; 0 = one launch per segment); RFO_SDDMM_TG_BF16 the
- *                        same for the matrix-core gradient (default 8).  The gradient is
- *                        summed per launch, so its rounding depends on them.
- *       RFO_OVERLAP      1 / 0 forces the overlapped / serial segment schedule of the
- *                        doubled adjoint (default: serial; bitwise equal)
- *       RFO_CPPL, RFO_CU, RFO_CGRID  probes per lane, rows or blocks per chunk and
- *                        workgroups of the complex shifted product (rational estimate)
+ *   - The library reads no environment variables.  Launch geometry and schedule
+ *     choices are context state (rfo_set_tuning); their defaults are the measured best.
  */
 #ifndef RFO_H
 #define RFO_H
@@ -133,7 +117,12 @@ int rfo_get_interval(const rfo_ctx *ctx, double *e_min, double *e_max);
 int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R,
                    const double *weights);
 
-/* Runs p = n_terms Chebyshev terms (p - 1 H.V steps) on every probe.
+/* Chebyshev moments, traces and density blocks (paper: Polynomial
+ * approximation, Eq. poly_PQ with S = I: the three-term recurrence
+ * y_0 = r, y_1 = H_hat r, y_{k+1} = 2 H_hat y_k - y_{k-1}, and P r ~ sum_k
+ * alpha^f_k y_k; Random approximation, Eq. random_density: M (.) P~ =
+ * sum_c w_c M (.) (P r_c) r_c^T; traces as in the file header).
+ * Runs p = n_terms Chebyshev terms (p - 1 H.V steps) on every probe.
  *   moments_out [s][p]  per-probe mu_{k,c} (nullable)
  *   NEF_out     [3]     N, E, F (nullable)
  *   density_out [nnzb][bd][bd]  M (.) P~, unsymmetrized (nullable; when NULL
@@ -277,6 +266,47 @@ int rfo_cg_stats(const rfo_ctx *ctx, int64_t *iterations, int64_t *solves);
  * enabled != 0 turns it on (the default), 0 makes every moment a direct
  * r . y_k over p - 1 steps. */
 int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
+
+/* Launch geometry and schedule of a context (for measurement; the defaults are the
+ * measured best).  value = -1 restores the default.  Keys and accepted values:
+ *   RFO_TUNE_PPL            probes per lane of the step kernels: 1, 2, 4
+ *   RFO_TUNE_RPI            1x1: rows per wave iteration (1, 2, 7); 9x9: blocks per chunk (1, 2)
+ *   RFO_TUNE_ROWS_PER_WG    block rows per scheduling unit of the step kernels (>= 1)
+ *   RFO_TUNE_GRID           resident workgroups of the step kernels (>= 8, rounded to 8)
+ *   RFO_TUNE_BF16_CHUNKS    BF16 steps: K chunks per iteration (1, 2, 4)
+ *   RFO_TUNE_SDDMM_PPL      probes per lane of the vector-unit outer products (1, 2)
+ *   RFO_TUNE_SDDMM_MFMA     0 keeps the BF16 segment gradient on the vector units (it then
+ *                           reads the FP32 vectors instead of their BF16 copies)
+ *   RFO_TUNE_SDDMM_STEPS    steps per launch of the segment gradient on the vector units
+ *                           (default 32; 0 = one launch per segment)
+ *   RFO_TUNE_SDDMM_STEPS_BF16  the same for the matrix-core segment gradient (default 8)
+ *   RFO_TUNE_OVERLAP        1: each segment's gradient of the doubled adjoint runs on a
+ *                           second stream beside the next segment's steps (default 0; the
+ *                           result is bitwise the serial one)
+ *   RFO_TUNE_CPLX_PPL, RFO_TUNE_CPLX_ROWS, RFO_TUNE_CPLX_GRID  probes per lane (1, 2), rows
+ *                           (1x1: 4, 8) or blocks (9x9: 1, 2) per chunk, and workgroups of
+ *                           the complex shifted product of the rational estimate
+ * Geometry changes only the order of FP64 sums (rounding).  The segment gradient's step
+ * groups and its matrix-core switch change how G is summed and so its rounding (and, for
+ * RFO_TUNE_SDDMM_MFMA = 0, which operands the BF16 gradient reads).
+ * Errors: RFO_E_INVALID for an unknown key or a value out of range. */
+typedef enum {
+  RFO_TUNE_PPL = 0,
+  RFO_TUNE_RPI = 1,
+  RFO_TUNE_ROWS_PER_WG = 2,
+  RFO_TUNE_GRID = 3,
+  RFO_TUNE_BF16_CHUNKS = 4,
+  RFO_TUNE_SDDMM_PPL = 5,
+  RFO_TUNE_SDDMM_MFMA = 6,
+  RFO_TUNE_SDDMM_STEPS = 7,
+  RFO_TUNE_SDDMM_STEPS_BF16 = 8,
+  RFO_TUNE_OVERLAP = 9,
+  RFO_TUNE_CPLX_PPL = 10,
+  RFO_TUNE_CPLX_ROWS = 11,
+  RFO_TUNE_CPLX_GRID = 12,
+  RFO_TUNE_COUNT = 13
+} rfo_tuning;
+int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value);
 
 /* Instrumentation: when enabled, the library records HIP events around each
  * run of consecutive Chebyshev-step launches on its stream.  rfo_step_timing

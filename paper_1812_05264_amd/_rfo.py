@@ -55,6 +55,7 @@ def load():
     lib.rfo_hf_forces.argtypes = [vp, vp, vp]
     lib.rfo_set_timing.argtypes = [vp, i32]
     lib.rfo_set_moment_doubling.argtypes = [vp, i32]
+    lib.rfo_set_tuning.argtypes = [vp, i32, i64]
     lib.rfo_traces_at.argtypes = [vp, dbl, dbl, ctypes.POINTER(dbl)]
     lib.rfo_set_overlap.argtypes = [vp, vp, dbl]
     lib.rfo_get_density_q.argtypes = [vp, vp]
@@ -64,11 +65,12 @@ def load():
     lib.rfo_rational_fit.argtypes = [i32, dbl, dbl, dbl, dbl, vp, vp, vp, vp]
     lib.rfo_rational_estimate.argtypes = [vp, dbl, i64, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
     lib.rfo_rational_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
-    for f in ("rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
-              "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing",
-              "rfo_step_timing", "rfo_set_moment_doubling", "rfo_traces_at", "rfo_set_overlap",
-              "rfo_get_density_q", "rfo_density_forces", "rfo_cg_stats", "rfo_rational_fit",
-              "rfo_rational_estimate", "rfo_rational_stats"):
+    for f in (
+        "rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
+        "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing", "rfo_step_timing",
+        "rfo_set_moment_doubling", "rfo_set_tuning", "rfo_traces_at", "rfo_set_overlap",
+        "rfo_get_density_q", "rfo_density_forces", "rfo_cg_stats", "rfo_rational_fit",
+        "rfo_rational_estimate", "rfo_rational_stats"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -293,6 +295,14 @@ class Engine:
     def set_moment_doubling(self, enabled=True):
         """Moment-only fermi_moments calls run floor(p/2) steps (doubling identities)."""
         self._check(self._lib.rfo_set_moment_doubling(self._ctx, 1 if enabled else 0))
+
+    TUNING = {"ppl": 0, "rpi": 1, "rows_per_wg": 2, "grid": 3, "bf16_chunks": 4, "sddmm_ppl": 5,
+              "sddmm_mfma": 6, "sddmm_steps": 7, "sddmm_steps_bf16": 8, "overlap": 9,
+              "cplx_ppl": 10, "cplx_rows": 11, "cplx_grid": 12}
+
+    def set_tuning(self, key, value=-1):
+        """Launch geometry / schedule of this context (rfo_set_tuning); -1 restores the default."""
+        self._check(self._lib.rfo_set_tuning(self._ctx, self.TUNING[key], int(value)))
 
     def set_timing(self, enabled=True):
         self._check(self._lib.rfo_set_timing(self._ctx, 1 if enabled else 0))

@@ -435,6 +435,32 @@ int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled) {
   return RFO_OK;
 }
 
+int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (key < 0 || key >= RFO_TUNE_COUNT) return fail(ctx, RFO_E_INVALID, "unknown tuning key %d", key);
+  bool ok = value == -1;
+  switch (key) {
+    case RFO_TUNE_PPL: ok = ok || value == 1 || value == 2 || value == 4; break;
+    case RFO_TUNE_RPI: ok = ok || value == 1 || value == 2 || value == 7; break;
+    case RFO_TUNE_ROWS_PER_WG: ok = ok || (value >= 1 && value <= 4096); break;
+    case RFO_TUNE_GRID: ok = ok || (value >= 8 && value <= (1 << 20)); break;
+    case RFO_TUNE_BF16_CHUNKS: ok = ok || value == 1 || value == 2 || value == 4; break;
+    case RFO_TUNE_SDDMM_PPL: ok = ok || value == 1 || value == 2; break;
+    case RFO_TUNE_SDDMM_MFMA: ok = ok || value == 0 || value == 1; break;
+    case RFO_TUNE_SDDMM_STEPS: ok = ok || (value >= 0 && value <= (1 << 20)); break;
+    case RFO_TUNE_SDDMM_STEPS_BF16: ok = ok || (value >= 0 && value <= (1 << 20)); break;
+    case RFO_TUNE_OVERLAP: ok = ok || value == 0 || value == 1; break;
+    case RFO_TUNE_CPLX_PPL: ok = ok || value == 1 || value == 2; break;
+    case RFO_TUNE_CPLX_ROWS: ok = ok || value == 1 || value == 2 || value == 4 || value == 8; break;
+    case RFO_TUNE_CPLX_GRID: ok = ok || (value >= 8 && value <= (1 << 20)); break;
+    default: break;
+  }
+  if (!ok) return fail(ctx, RFO_E_INVALID, "tuning value %lld out of range for key %d", (long long)value, key);
+  ctx->tune[key] = key == RFO_TUNE_GRID || key == RFO_TUNE_CPLX_GRID ? (value < 0 ? -1 : value / 8 * 8) : value;
+  return RFO_OK;
+}
+
 int rfo_set_timing(rfo_ctx *ctx, int enabled) {
   if (!ctx) return RFO_E_INVALID;
   ctx->timing = enabled != 0;

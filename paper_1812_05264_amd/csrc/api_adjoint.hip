@@ -29,8 +29,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   // step-group launches: FP64 10.05 against 9.29 s, FP32 5.63 against 5.46 s, BF16
   // 4.04 against 3.96 s (the persistent step kernels lose the CUs the gradient holds),
   // so the serial schedule is the default and the overlap is taken on request.
-  bool overlap = false;
-  if (const char *env = getenv("RFO_OVERLAP")) overlap = Q > 1 && atoi(env) != 0;
+  const bool overlap = Q > 1 && tuned(ctx, RFO_TUNE_OVERLAP, 0) != 0;
   const int n_sets = overlap ? 2 : 1;
   // vector slots: n_sets x (ys [m + 2] | zs [m + 2]) | checkpoints [2 (Q - 1)]
   const int64_t n_ys = m + 2, n_zs = m + 2, n_ck = Q > 1 ? 2 * (Q - 1) : 0;
@@ -207,9 +206,9 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
       sm.w0 = ctx->w_uniform;
       sm.G = sd.G;
       sm.accumulate = sd.accumulate;
-      HIPCHK(launch_sddmm_bf16_segment(sm, pl.slot_bytes, sd_stream));
+      HIPCHK(launch_sddmm_bf16_segment(ctx, sm, pl.slot_bytes, sd_stream));
     } else {
-      HIPCHK(launch_sddmm_segment(kp, sd, pl.slot_bytes, sd_stream));
+      HIPCHK(launch_sddmm_segment(ctx, kp, sd, pl.slot_bytes, sd_stream));
     }
     if (overlap) {
       HIPCHK(hipEventRecord(ctx->ev_sd[cur], ctx->side));
@@ -372,7 +371,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       a.nzlist = P<int64_t>(ctx->nz_up);
       a.nlist = ctx->n_up;
       a.ppl = sddmm_ppl(ctx);
-      HIPCHK(launch_sddmm_segment(kp, a, pl.slot_bytes, ctx->stream));
+      HIPCHK(launch_sddmm_segment(ctx, kp, a, pl.slot_bytes, ctx->stream));
       if (q > 0) {
         // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}
         HIPCHK(hipMemcpyAsync(zs(m), zs(0), vb, hipMemcpyDeviceToDevice, ctx->stream));

@@ -59,6 +59,8 @@ struct rfo_ctx {
   bool has_grad = false;
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
+  // launch geometry and schedule (rfo_set_tuning); -1 = the measured default
+  int64_t tune[RFO_TUNE_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
   // nonorthogonal basis: overlap S on H's pattern, S^{-1} by conjugate gradients
   bool has_s = false, interval_given = false, has_q = false, has_dens = false;
   double cg_tol = 1e-13;
@@ -156,6 +158,11 @@ inline void release(DevBuf &b) {
   b.bytes = 0;
 }
 
+// a tuning value of the context, or def when it is at its default
+inline int64_t tuned(const rfo_ctx *c, int key, int64_t def) {
+  return c->tune[key] >= 0 ? c->tune[key] : def;
+}
+
 template <typename T>
 T *P(DevBuf &b) {
   return static_cast<T *>(b.p);
@@ -185,7 +192,7 @@ inline Plan make_plan(const rfo_ctx *c) {
   // 16 bytes per lane (FP64) or 16 (FP32, 9x9: 32 measured best) per gather
   int want = 16 / pl.vt_bytes;
   if (c->bd == 9 && c->prec != RFO_FP64) want = 4;
-  if (const char *env = getenv("RFO_PPL")) want = atoi(env);
+  want = (int)tuned(c, RFO_TUNE_PPL, want);
   pl.ppl = 1;
   for (int q = 4; q >= 1; q >>= 1)
     if (q <= want && c->sp % (64 * q) == 0) {
@@ -196,18 +203,15 @@ inline Plan make_plan(const rfo_ctx *c) {
   // rows per workgroup: small enough that the resident workgroups of an XCD
   // cover a narrow band of rows, large enough to keep the moment partials small
   int64_t rows = c->bd == 1 ? 8 : 4;
-  if (const char *env = getenv("RFO_ROWS_PER_WG")) {
-    const int64_t r = atoll(env);
-    if (r >= 1) rows = r;
-  }
+  rows = tuned(c, RFO_TUNE_ROWS_PER_WG, rows);
   pl.rows_per_wg = (int)rows;
   pl.n_rg = (int)((c->nb + rows - 1) / rows);
   pl.ring = 32;
   // 1x1 blocks: rows per wave iteration, or 7 when every row fits one chunk of 7
   // neighbours (measured faster on the 7-point lattice); 9x9: blocks per chunk
   pl.rpi = c->bd == 1 ? (c->max_row <= 7 ? 7 : 1) : 2;
-  if (const char *env = getenv("RFO_RPI")) {
-    const int r = atoi(env);
+  {
+    const int r = (int)tuned(c, RFO_TUNE_RPI, pl.rpi);
     if (r == 1 || r == 2 || (c->bd == 1 && r == 7)) pl.rpi = r;
   }
   pl.n_pt_step = pl.n_pt;
@@ -219,10 +223,7 @@ inline Plan make_plan(const rfo_ctx *c) {
     pl.ntiles = 4;
     pl.rpi = 2;
     pl.n_pt_step = c->sp / (16 * pl.ntiles);
-    if (const char *env = getenv("RFO_BF16_U")) {
-      const int u = atoi(env);
-      if (u == 1 || u == 2 || u == 4) pl.rpi = u;
-    }
+    pl.rpi = (int)tuned(c, RFO_TUNE_BF16_CHUNKS, pl.rpi);
     occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi));
   } else {
     occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi));
@@ -231,7 +232,7 @@ inline Plan make_plan(const rfo_ctx *c) {
   // most four per CU: more workgroups widen the band of rows in flight on an XCD
   // past what its L2 holds of their neighbour rows (measured slower)
   int64_t grid = (int64_t)c->cus * std::min(occ, 4);
-  if (const char *env = getenv("RFO_GRID")) grid = std::max<int64_t>(8, atoll(env));
+  grid = tuned(c, RFO_TUNE_GRID, grid);
   const int64_t units = (int64_t)pl.n_pt_step * pl.n_rg;
   grid = std::min(grid, (units + 7) / 8 * 8);
   grid = std::max<int64_t>(8, grid / 8 * 8);
@@ -284,24 +285,17 @@ inline int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 :
 inline bool use_mfma_sddmm(const rfo_ctx *c) {
   if (c->bd != 9 || c->prec != RFO_BF16 || c->w_uniform == 0.0 || !c->has_up_grp) return false;
   if (c->sp % 32 != 0) return false;
-  if (const char *env = getenv("RFO_SDDMM_MFMA")) return atoi(env) != 0;
-  return true;
+  return tuned(c, RFO_TUNE_SDDMM_MFMA, 1) != 0;
 }
 
-// The segment gradient in launches of at most sddmm_steps() steps each (8 for
-// the BF16 kernel): all resident waves then work on the same few steps, so the
+// The segment gradient in launches of at most 32 steps each (8 for the BF16
+// kernel; RFO_TUNE_SDDMM_STEPS, RFO_TUNE_SDDMM_STEPS_BF16): all resident waves then work on the same few steps, so the
 // rows of X_t and Y_t that the blocks of a band of block rows share are read
 // while the L2 holds them.  Measured on the 16,000-atom cluster at 8000 terms
 // (segments of 64 steps).
-inline int sddmm_steps() {
-  int tg = 32;
-  if (const char *env = getenv("RFO_SDDMM_TG")) tg = atoi(env);
-  return tg;
-}
-
-inline hipError_t launch_sddmm_segment(int precision, const rfo::SddmmArgs &a, size_t slot_bytes,
-                                       hipStream_t s) {
-  const int tg = sddmm_steps();
+inline hipError_t launch_sddmm_segment(const rfo_ctx *c, int precision, const rfo::SddmmArgs &a,
+                                       size_t slot_bytes, hipStream_t s) {
+  const int tg = (int)tuned(c, RFO_TUNE_SDDMM_STEPS, 32);
   if (tg <= 0 || a.count <= tg) return rfo::launch_sddmm(precision, a, s);
   rfo::SddmmArgs b = a;
   for (int t0 = 0; t0 < a.count; t0 += tg) {
@@ -316,10 +310,9 @@ inline hipError_t launch_sddmm_segment(int precision, const rfo::SddmmArgs &a, s
   return hipSuccess;
 }
 
-inline hipError_t launch_sddmm_bf16_segment(const rfo::SddmmMfmaArgs &a, size_t slot_bytes,
-                                            hipStream_t s) {
-  int tg = 8;
-  if (const char *env = getenv("RFO_SDDMM_TG_BF16")) tg = atoi(env);
+inline hipError_t launch_sddmm_bf16_segment(const rfo_ctx *c, const rfo::SddmmMfmaArgs &a,
+                                            size_t slot_bytes, hipStream_t s) {
+  const int tg = (int)tuned(c, RFO_TUNE_SDDMM_STEPS_BF16, 8);
   if (tg <= 0 || a.count <= tg) return rfo::launch_sddmm_bf16(a, s);
   rfo::SddmmMfmaArgs b = a;
   for (int t0 = 0; t0 < a.count; t0 += tg) {
@@ -335,9 +328,8 @@ inline hipError_t launch_sddmm_bf16_segment(const rfo::SddmmMfmaArgs &a, size_t 
 }
 
 inline int sddmm_ppl(const rfo_ctx *c) {
-  int ppl = (c->sp % 128 == 0) ? 2 : 1;
-  if (const char *env = getenv("RFO_SDDMM_PPL")) ppl = atoi(env) == 2 && c->sp % 128 == 0 ? 2 : 1;
-  return ppl;
+  const int64_t want = tuned(c, RFO_TUNE_SDDMM_PPL, 2);
+  return (want == 2 && c->sp % 128 == 0) ? 2 : 1;
 }
 
 inline hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::StepArgs &a) {
@@ -568,7 +560,8 @@ inline int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bo
   return RFO_OK;
 }
 
-inline int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) {
+// argument and state checks shared by the calls that run the recurrence
+inline int validate_call(rfo_ctx *ctx, double T, double mu, int64_t p) {
   if (!ctx) return RFO_E_INVALID;
   if (!ctx->has_h) return fail(ctx, RFO_E_STATE, "no Hamiltonian: call rfo_set_hamiltonian first");
   if (!ctx->has_r) return fail(ctx, RFO_E_STATE, "no probes: call rfo_set_probes first");
@@ -576,6 +569,11 @@ inline int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) 
   if (!std::isfinite(mu)) return fail(ctx, RFO_E_INVALID, "mu must be finite");
   if (p < 1 || p > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_terms must be in [1, 2^20]");
   HIPCHK(hipSetDevice(ctx->device));
+  return RFO_OK;
+}
+
+inline int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) {
+  TRY(validate_call(ctx, T, mu, p));
   pl = make_plan(ctx);
   const int64_t nq = 4 * p;
   TRY(ensure(ctx, ctx->ring, (size_t)pl.ring * pl.grid * ctx->sp * sizeof(double)));

@@ -143,10 +143,10 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   w.ppl = sp % 128 == 0 ? 2 : 1;
   // with an overlap the 9x9 product keeps four row sums per probe: one probe per lane
   if (ctx->has_s && ctx->bd == 9) w.ppl = 1;
-  if (const char *env = getenv("RFO_CPPL")) w.ppl = atoi(env) == 2 && sp % 128 == 0 ? 2 : 1;
+  if (ctx->tune[RFO_TUNE_CPLX_PPL] >= 0) w.ppl = ctx->tune[RFO_TUNE_CPLX_PPL] == 2 && sp % 128 == 0 ? 2 : 1;
   w.u = ctx->bd == 1 ? 4 : 1;
-  if (const char *env = getenv("RFO_CU")) {
-    const int u = atoi(env);
+  {
+    const int u = (int)tuned(ctx, RFO_TUNE_CPLX_ROWS, w.u);
     if (ctx->bd == 1 ? (u == 4 || u == 8) : (u == 1 || u == 2)) w.u = u;
   }
   memset(&w.ca, 0, sizeof(w.ca));
@@ -163,7 +163,7 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   {
     const int occ = std::max(1, rfo::cspmm_blocks_per_cu(ctx->bd, w.ppl, w.u, ctx->has_s));
     int64_t grid = (int64_t)ctx->cus * std::min(occ, 4);
-    if (const char *env = getenv("RFO_CGRID")) grid = std::max<int64_t>(8, atoll(env));
+    grid = tuned(ctx, RFO_TUNE_CPLX_GRID, grid);
     const int64_t units = (int64_t)w.ca.n_pt * w.ca.n_rg;
     grid = std::min(grid, (units + 7) / 8 * 8);
     w.ca.grid = (int)std::max<int64_t>(8, grid / 8 * 8);

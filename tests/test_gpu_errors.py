@@ -88,3 +88,16 @@ def test_gershgorin_fallback_contains_spectrum():
     c, h = 0.5 * (lo + hi), 1.01 * 0.5 * (hi - lo)
     assert abs(a - (c - h)) < 1e-12 and abs(b - (c + h)) < 1e-12
     assert a < w[0] and w[-1] < b
+
+
+def test_tuning_keys_and_values_are_validated():
+    import paper_1812_05264_amd as pkg
+    banner("tuning validation")
+    eng = engine_or_skip()
+    for key, bad in (("ppl", 3), ("grid", 4), ("sddmm_mfma", 2), ("overlap", 5), ("cplx_rows", 3)):
+        with pytest.raises(pkg.RfoError):
+            eng.set_tuning(key, bad)
+    with pytest.raises(pkg.RfoError):
+        eng._check(eng._lib.rfo_set_tuning(eng._ctx, 99, 1))
+    for key in eng.TUNING:
+        eng.set_tuning(key, -1)
