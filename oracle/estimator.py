@@ -154,3 +154,65 @@ def estimate(bsr, R, T, mu, n_terms, weights=None, density=False, gradient=False
         out["dFdH"] = G
         out["F_grad_pass"] = F2
     return out
+
+
+def free_energy_gradient_rows(Hhat, R, weights, beta, n_terms, bsr, e_min, e_max, block_rows):
+    """(F, nz, G_rows): the gradient of free_energy_gradient on the stored blocks of the given
+    block rows only, for systems too large to hold every y_j and U_m(H_hat) r.
+
+    The same U-polynomial form and the same sums: x_j = (2 - delta_j0) sum_m beta_{j+1+m} u_m
+    with u_m = U_m(H_hat) r, and G_IJ = sum_j sum_c w_c x_{j,c}[I] y_{j,c}[J]^T times
+    2/(e_max - e_min).  Each vector is formed whole by the recurrence; only the entries of
+    the rows I (for u_m) and of their neighbour rows J (for y_j) are kept.
+    nz lists the selected blocks (in pattern order), G_rows is [len(nz), bd, bd]."""
+    R = np.asarray(R, dtype=np.float64)
+    n, s = R.shape
+    p = n_terms
+    bd = bsr.block_dim
+    rows = bsr.block_rows()
+    cols = bsr.col_idx.astype(np.int64)
+    sel = np.isin(rows, np.asarray(block_rows, dtype=np.int64))
+    nz = np.nonzero(sel)[0]
+    need_I = np.unique(rows[nz])
+    need_J = np.unique(cols[nz])
+    oI = (need_I[:, None] * bd + np.arange(bd)[None, :]).ravel()
+    oJ = (need_J[:, None] * bd + np.arange(bd)[None, :]).ravel()
+    w = np.asarray(weights, dtype=np.float64)
+    F_c = np.zeros(s)
+    ysJ = np.empty((max(p - 1, 1), oJ.size, s))
+    for k, y in enumerate(chebyshev_vectors(Hhat, R, p)):
+        F_c += beta[k] * np.einsum("ic,ic->c", y, R)
+        if k < p - 1:
+            ysJ[k] = y[oJ]
+    F = float(np.dot(w, F_c))
+    if p < 2:
+        return F, nz, np.zeros((nz.size, bd, bd))
+    # u_m = U_m(H_hat) r:  U_0 = 1, U_1 = 2x, U_{m+1} = 2x U_m - U_{m-1}
+    usI = np.empty((p - 1, oI.size, s))
+    u_prev = u = None
+    for m in range(p - 1):
+        if m == 0:
+            u_new = R
+        elif m == 1:
+            u_new = 2.0 * (Hhat @ R)
+        else:
+            u_new = 2.0 * (Hhat @ u) - u_prev
+        u_prev, u = u, u_new
+        usI[m] = u_new[oI]
+    # x_j = (2 - delta_j0) sum_{m=0}^{p-2-j} beta_{j+1+m} u_m,  j = 0..p-2
+    jj = np.arange(p - 1)[:, None]
+    mm = np.arange(p - 1)[None, :]
+    idx = jj + 1 + mm
+    B = np.where(idx <= p - 1, np.asarray(beta)[np.minimum(idx, p - 1)], 0.0)
+    B[1:] *= 2.0
+    xsI = (B @ usI.reshape(p - 1, -1)).reshape(p - 1, oI.size, s)
+    posI = {int(I): i for i, I in enumerate(need_I)}
+    posJ = {int(J): i for i, J in enumerate(need_J)}
+    G = np.empty((nz.size, bd, bd))
+    for t, z in enumerate(nz):
+        i0 = posI[int(rows[z])] * bd
+        j0 = posJ[int(cols[z])] * bd
+        X = xsI[:, i0:i0 + bd, :] * w[None, None, :]
+        Y = ysJ[:, j0:j0 + bd, :]
+        G[t] = np.einsum("jac,jbc->ab", X, Y)
+    return F, nz, (2.0 / (e_max - e_min)) * G

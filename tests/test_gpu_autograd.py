@@ -10,7 +10,7 @@ import pytest
 
 from oracle import estimator as est
 from oracle import forces as ofo
-from tests.gpu_common import banner, engine_or_skip, load_hamiltonian, rel
+from tests.gpu_common import banner, check_rows, engine_or_skip, load_hamiltonian
 from workloads import cu_cluster, rademacher
 
 pytestmark = pytest.mark.gpu
@@ -35,8 +35,8 @@ def test_autograd_forces_match_kernel_and_oracle():
     o = est.estimate(H, R, T, mu, p, gradient=True)
     f_oracle = ofo.hf_forces(H, o["dFdH"], cl.dH_dR())
     assert abs(F.item() - o["F"]) < 1e-10 * abs(o["F"])
-    assert rel(f_auto, f_oracle) < 1e-10
-    assert rel(f_kernel, f_oracle) < 1e-10
+    check_rows(f_auto, f_oracle, what="autograd forces")
+    check_rows(f_kernel, f_oracle, what="kernel forces")
 
 
 def test_forces_match_finite_differences_on_every_atom():

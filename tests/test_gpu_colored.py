@@ -10,7 +10,7 @@ import pytest
 from oracle import estimator as est
 from oracle import forces as ofo
 from oracle import trunc
-from tests.gpu_common import TOL, banner, engine_or_skip, load_hamiltonian, rel
+from tests.gpu_common import TOL, banner, check_blocks, check_moments, check_rows, engine_or_skip, load_hamiltonian
 from workloads import cu_cluster, rademacher_signs
 
 pytestmark = pytest.mark.gpu
@@ -35,14 +35,14 @@ def test_colored_probes_match_oracle(doubling):
     T, mu, p = 0.3, 0.3, 90
     g = eng.fermi_moments(T, mu, p, moments=True, density=True)
     o = est.estimate(H, R, T, mu, p, weights=w, density=True, gradient=True)
-    assert rel(g["moments"], o["moments"]) < TOL
-    assert rel(g["density"], o["density"]) < TOL
+    check_moments(g["moments"], o["moments"])
+    check_blocks(g["density"], o["density"])
     for key in ("N", "E", "F"):
         assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
     e = eng.energy_and_dEdH(T, mu, p)
-    assert rel(e["dFdH"], o["dFdH"]) < TOL
+    check_blocks(e["dFdH"], o["dFdH"])
     D = cl.dH_dR()
-    assert rel(eng.hf_forces(D), ofo.hf_forces(H, o["dFdH"], D)) < TOL
+    check_rows(eng.hf_forces(D), ofo.hf_forces(H, o["dFdH"], D), what="forces")
 
 
 def test_colored_error_is_the_same_colour_sum():

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import overlap as ov
-from tests.gpu_common import TOL, banner, engine_or_skip, rel
+from tests.gpu_common import TOL, banner, check_blocks, check_moments, engine_or_skip
 from workloads import BSR, cu_cluster, identity_probes, rademacher, simple_cubic
 from workloads.overlap import dS_dR, overlap_values, pencil_interval
 
@@ -49,11 +49,11 @@ def test_overlap_matches_oracle(case):
     g = eng.fermi_moments(T, mu, p, moments=True, density=True)
     Q = eng.density_q()
     o = ov.estimate(H, S, R, T, mu, p, density=True)
-    assert rel(g["moments"], o["moments"]) < TOL
+    check_moments(g["moments"], o["moments"])
     for key in ("N", "E", "F"):
         assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
-    assert rel(g["density"], o["density"]) < TOL
-    assert rel(Q, o["density_Q"]) < TOL
+    check_blocks(g["density"], o["density"])
+    check_blocks(Q, o["density_Q"])
     it, solves = eng.cg_stats()
     print(f"{case}: {solves} CG solves, {it / max(1, solves):.1f} iterations each")
     t = eng.traces_at(0.25, 0.0)                      # stored moments, new (T, mu)
@@ -89,7 +89,8 @@ def test_unit_overlap_equals_orthogonal_path():
     b = eng.fermi_moments(0.3, 0.2, 70, moments=True, density=True)
     eng.set_overlap(None)
     c = eng.fermi_moments(0.3, 0.2, 70, moments=True, density=True)
-    assert rel(b["moments"], a["moments"]) < 1e-12 and rel(b["density"], a["density"]) < 1e-12
+    check_moments(b["moments"], a["moments"], 1e-12)
+    check_blocks(b["density"], a["density"], 1e-12)
     assert np.array_equal(c["moments"], a["moments"])
 
 

@@ -12,7 +12,7 @@ from oracle import closed_form as cf
 from oracle import estimator as est
 from oracle import forces as ofo
 from oracle import trunc
-from tests.gpu_common import TOL, banner, engine_or_skip, load_hamiltonian, rel
+from tests.gpu_common import TOL, banner, check_blocks, check_moments, check_rows, engine_or_skip, load_hamiltonian, rel
 from workloads import cu_cluster, identity_probes, rademacher, random_graph, simple_cubic
 
 pytestmark = pytest.mark.gpu
@@ -42,13 +42,13 @@ def test_fermi_moments_match_oracle(name):
     eng.set_probes(R)
     g = eng.fermi_moments(T, mu, p, moments=True, density=True)
     o = est.estimate(H, R, T, mu, p, density=True)
-    assert rel(g["moments"], o["moments"]) < TOL
+    check_moments(g["moments"], o["moments"])
     for key in ("N", "E", "F"):
         assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
-    assert rel(g["density"], o["density"]) < TOL
+    check_blocks(g["density"], o["density"])
     # without density the moments come from the doubling identities
     d = eng.fermi_moments(T, mu, p, moments=True)
-    assert rel(d["moments"], o["moments"]) < TOL
+    check_moments(d["moments"], o["moments"])
     for key in ("N", "E", "F"):
         assert abs(d[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
 
@@ -66,8 +66,8 @@ def test_density_short_series(bd):
     for p in range(1, 9):
         g = eng.fermi_moments(0.2, 0.1, p, moments=True, density=True)
         o = est.estimate(H, R, 0.2, 0.1, p, density=True)
-        assert rel(g["moments"], o["moments"]) < TOL, p
-        assert rel(g["density"], o["density"]) < TOL, p
+        check_moments(g["moments"], o["moments"], what=f"moments p={p}")
+        check_blocks(g["density"], o["density"], what=f"density p={p}")
 
 
 @pytest.mark.parametrize("bd", [1, 9])
@@ -84,11 +84,11 @@ def test_doubling_short_series_and_direct_path(bd):
     for p in list(range(1, 10)) + [64, 65]:
         g = eng.fermi_moments(0.2, 0.1, p, moments=True)
         o = est.estimate(H, R, 0.2, 0.1, p)
-        assert rel(g["moments"], o["moments"]) < TOL, p
+        check_moments(g["moments"], o["moments"], what=f"moments p={p}")
         eng.set_moment_doubling(False)
         d = eng.fermi_moments(0.2, 0.1, p, moments=True)
         eng.set_moment_doubling(True)
-        assert rel(g["moments"], d["moments"]) < 1e-13, p
+        check_moments(g["moments"], d["moments"], 1e-13, what=f"doubled vs direct p={p}")
         assert abs(g["F"] - d["F"]) <= 1e-12 * abs(d["F"]), p
 
 
@@ -182,12 +182,12 @@ def test_gradient_matches_oracle(name, doubling):
     g = eng.energy_and_dEdH(T, mu, p)
     o = est.estimate(H, R, T, mu, p, gradient=True)
     assert abs(g["F"] - o["F"]) <= TOL * max(1.0, abs(o["F"]))
-    assert rel(g["dFdH"], o["dFdH"]) < TOL
+    check_blocks(g["dFdH"], o["dFdH"])
     if hasattr(obj, "dH_dR"):
         D = obj.dH_dR()
         fg = eng.hf_forces(D)
         fo = ofo.hf_forces(H, o["dFdH"], D)
-        assert rel(fg, fo) < TOL
+        check_rows(fg, fo, what="forces")
         assert np.max(np.abs(fg.sum(axis=0))) < 1e-10 * np.max(np.abs(fg))
 
 
@@ -223,7 +223,7 @@ def test_moments_bitwise_deterministic():
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
-def test_gradient_segments_overlapped_equal_serial(prec, monkeypatch):
+def test_gradient_segments_overlapped_equal_serial(prec):
     """The doubled adjoint can run each segment's gradient on a second stream while
     the next segment replays on the first (two alternating sets of y, z slots, on
     request): the result is bitwise the serial one, and the FP64 gradient matches
@@ -236,28 +236,28 @@ def test_gradient_segments_overlapped_equal_serial(prec, monkeypatch):
     eng = engine_or_skip()
     load_hamiltonian(eng, H, precision=prec)
     eng.set_probes(R)
-    monkeypatch.setenv("RFO_OVERLAP", "1")
+    eng.set_tuning("overlap", 1)
     a = eng.energy_and_dEdH(T, mu, p)
     fa = eng.hf_forces(cl.dH_dR())
-    monkeypatch.setenv("RFO_OVERLAP", "0")
+    eng.set_tuning("overlap", 0)
     b = eng.energy_and_dEdH(T, mu, p)
-    monkeypatch.setenv("RFO_OVERLAP", "1")
+    eng.set_tuning("overlap", 1)
     assert a["F"] == b["F"]
     assert np.array_equal(a["dFdH"], b["dFdH"])
     c = eng.energy_and_dEdH(T, mu, p)    # repeated overlapped call
-    monkeypatch.delenv("RFO_OVERLAP")
+    eng.set_tuning("overlap", -1)
     assert np.array_equal(a["dFdH"], c["dFdH"])
     d = eng.energy_and_dEdH(T, mu, p)    # the precision's default schedule
     assert np.array_equal(a["dFdH"], d["dFdH"])
     if prec == "fp64":
         o = est.estimate(H, R, T, mu, p, gradient=True)
-        assert rel(a["dFdH"], o["dFdH"]) < TOL
-        assert rel(fa, ofo.hf_forces(H, o["dFdH"], cl.dH_dR())) < TOL
+        check_blocks(a["dFdH"], o["dFdH"])
+        check_rows(fa, ofo.hf_forces(H, o["dFdH"], cl.dH_dR()), what="forces")
 
 
 @pytest.mark.parametrize("prec,doubling", [("fp64", True), ("fp64", False), ("fp32", True),
                                            ("bf16", True)])
-def test_gradient_segments_in_step_groups(prec, doubling, monkeypatch):
+def test_gradient_segments_in_step_groups(prec, doubling):
     """Each segment's gradient runs in launches of a few steps (the per-launch sums
     are added to G in step order): against one launch per segment the result
     differs only by FP64 rounding, F is unchanged, and in FP64 both match the
@@ -271,12 +271,12 @@ def test_gradient_segments_in_step_groups(prec, doubling, monkeypatch):
     load_hamiltonian(eng, H, precision=prec)
     eng.set_probes(R)
     eng.set_moment_doubling(doubling)
-    monkeypatch.setenv("RFO_SDDMM_TG", "0")
-    monkeypatch.setenv("RFO_SDDMM_TG_BF16", "0")
+    eng.set_tuning("sddmm_steps", 0)
+    eng.set_tuning("sddmm_steps_bf16", 0)
     whole = eng.energy_and_dEdH(T, mu, p)
     for tg in ("1", "2", "5"):
-        monkeypatch.setenv("RFO_SDDMM_TG", tg)
-        monkeypatch.setenv("RFO_SDDMM_TG_BF16", tg)
+        eng.set_tuning("sddmm_steps", int(tg))
+        eng.set_tuning("sddmm_steps_bf16", int(tg))
         g = eng.energy_and_dEdH(T, mu, p)
         assert g["F"] == whole["F"], tg
         e = rel(g["dFdH"], whole["dFdH"])
@@ -284,5 +284,5 @@ def test_gradient_segments_in_step_groups(prec, doubling, monkeypatch):
         assert e < 1e-12, tg
     if prec == "fp64":
         o = est.estimate(H, R, T, mu, p, gradient=True)
-        assert rel(whole["dFdH"], o["dFdH"]) < TOL
-        assert rel(g["dFdH"], o["dFdH"]) < TOL
+        check_blocks(whole["dFdH"], o["dFdH"])
+        check_blocks(g["dFdH"], o["dFdH"])

@@ -101,7 +101,7 @@ def test_bf16_gradient_against_fp64():
 
 
 @pytest.mark.parametrize("s", [64, 200, 256])
-def test_bf16_segment_gradient_on_matrix_cores(s, monkeypatch):
+def test_bf16_segment_gradient_on_matrix_cores(s):
     """The segment gradient of BF16 steps runs on the matrix cores (from the
     vectors' BF16 copies) when every probe has the same weight: against the VALU
     contraction of the FP32 vectors of the same steps and against the FP64
@@ -119,9 +119,9 @@ def test_bf16_segment_gradient_on_matrix_cores(s, monkeypatch):
     load_hamiltonian(eng, H, precision="bf16")
     eng.set_probes(R)
     g = eng.energy_and_dEdH(T, mu, p)
-    monkeypatch.setenv("RFO_SDDMM_MFMA", "0")
+    eng.set_tuning("sddmm_mfma", 0)
     v = eng.energy_and_dEdH(T, mu, p)
-    monkeypatch.delenv("RFO_SDDMM_MFMA")
+    eng.set_tuning("sddmm_mfma", -1)
     assert g["F"] == v["F"]                               # the steps are the same
     e_v, e_o = rel(g["dFdH"], v["dFdH"]), rel(g["dFdH"], o["dFdH"])
     print(f"bf16 s={s}: matrix cores vs VALU {e_v:.2e}, vs oracle {e_o:.2e} "

@@ -164,3 +164,29 @@ def test_doubling_identities_hold_for_oracle_vectors():
         assert np.allclose(two_j, mu[:, 2 * j], rtol=0, atol=1e-11 * H.n)
         two_jm1 = 2 * np.einsum("ic,ic->c", ys[j], ys[j - 1]) - mu[:, 1]
         assert np.allclose(two_jm1, mu[:, 2 * j - 1], rtol=0, atol=1e-11 * H.n)
+
+
+def test_gradient_on_selected_rows(cu13):
+    """The row-restricted gradient (used for the full-size fixture): with identity probes it
+    equals the truncated-series gradient (eigenbasis) on the selected block rows, and with
+    Rademacher probes and unequal weights it equals the whole-pattern gradient on them."""
+    H = cu13
+    T, mu, p = 0.3, 0.2, 96
+    Hh = est.mapped_hamiltonian(H)
+    _, _, bg = fm.fermi_coefficient_sets(H.e_min, H.e_max, T, mu, p)
+    tr = trunc.observables(H.to_dense(), H.e_min, H.e_max, T, mu, p)
+    sel = [0, 4, 12]
+    F, nz, G = est.free_energy_gradient_rows(Hh, identity_probes(H.n), np.ones(H.n), bg, p, H,
+                                             H.e_min, H.e_max, sel)
+    rows, cols, bd = H.block_rows(), H.col_idx, H.block_dim
+    assert set(rows[nz].tolist()) == set(sel) and nz.size == np.isin(rows, sel).sum()
+    want = np.stack([tr["dFdH"][bd * r:bd * r + bd, bd * c:bd * c + bd]
+                     for r, c in zip(rows[nz], cols[nz])])
+    assert np.max(np.abs(G - want)) < 1e-11
+    assert abs(F - tr["F"]) < 1e-10 * abs(tr["F"])
+    R = rademacher(H.n, 3, config_id=84)
+    w = np.array([0.5, 1.0, 0.25])
+    F_all, G_all = est.free_energy_gradient(Hh, R, w, bg, p, H, H.e_min, H.e_max)
+    F2, nz2, G2 = est.free_energy_gradient_rows(Hh, R, w, bg, p, H, H.e_min, H.e_max, [1, 12])
+    assert abs(F2 - F_all) < 1e-13 * abs(F_all)
+    assert np.max(np.abs(G2 - G_all[nz2])) < 1e-13 * np.max(np.abs(G_all))

@@ -42,3 +42,35 @@ def test_library_fit_is_accurate(pkg):
 def test_library_fit_rejects_bad_arguments(pkg, args):
     with pytest.raises(pkg.RfoError):
         pkg.rational_fit(*args)
+
+
+@pytest.mark.parametrize("T,mu,a,b", [(0.05, 0.2, -4.0, 6.0), (0.025, 1.165, -10.0, 10.0)])
+def test_library_fit_approximates_f_and_g_in_closed_form(pkg, T, mu, a, b):
+    """Independent of the oracle's fit: the library's residue-pole form, summed here directly
+    (f0 + 2 Re sum res_f/(x - z), g0 + g1 x + 2 Re sum res_g/(x - z)), against the closed forms
+    f = 1 - tanh((x - mu)/2T) and g = -2T ln(1 + exp(-(x - mu)/T)) on the whole interval.  The
+    error must fall at the trapezoid rule's geometric rate exp(-pi^2 n / (ln(M/m) + 3)),
+    M/m = ((e - mu)^2 + (pi T)^2)/(pi T)^2 at the farther end (within a constant factor), down
+    to rounding.  This pins the g residues without the oracle's derivation."""
+    x = np.linspace(a, b, 20001)
+    X = x - mu
+    f_ex = 1.0 - np.tanh(X / (2 * T))
+    g_ex = -2.0 * T * np.logaddexp(0.0, -X / T)
+    M = max((a - mu) ** 2, (b - mu) ** 2) + (np.pi * T) ** 2
+    m = (np.pi * T) ** 2
+    prev = None
+    for n in (10, 20, 30, 45, 60):
+        fit = pkg.rational_fit(n, T, mu, a, b)
+        z = fit["poles"]
+        inv = 1.0 / (x[:, None] - z[None, :])
+        f = fit["f0"] + 2.0 * np.real(inv @ fit["res_f"])
+        g = fit["g0"] + fit["g1"] * x + 2.0 * np.real(inv @ fit["res_g"])
+        ef = np.max(np.abs(f - f_ex))
+        eg = np.max(np.abs(g - g_ex))
+        model = np.exp(-np.pi ** 2 * n / (np.log(M / m) + 3.0))
+        floor = 1e-13 * max(1.0, np.max(np.abs(g_ex)))
+        assert ef <= max(10.0 * model, 1e-14), (n, ef, model)
+        assert eg <= max(1e3 * model, floor), (n, eg, model)
+        if prev is not None and prev > 1e3 * floor:
+            assert eg < 0.1 * prev, (n, eg, prev)   # still converging geometrically
+        prev = eg

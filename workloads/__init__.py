@@ -15,7 +15,7 @@ Random streams follow one convention: numpy PCG64 seeded with
 from .bsr import BSR
 from .lattice import simple_cubic
 from .graph import random_graph
-from .cluster import CuCluster, cu_cluster
+from .cluster import CuCluster, cu_cluster, finite_difference_atoms
 from .probes import rademacher, identity_probes, rademacher_signs
 from .configs import CONFIGS, get_config
 
@@ -25,6 +25,7 @@ __all__ = [
     "random_graph",
     "CuCluster",
     "cu_cluster",
+    "finite_difference_atoms",
     "rademacher",
     "rademacher_signs",
     "identity_probes",

@@ -229,3 +229,14 @@ def cu_cluster(n_atoms: int, config_id: int = 3, a: float = 3.61, lam: float = L
     cl.center = _round6(0.5 * (lo + hi))
     cl.half = _round6(1.01 * 0.5 * (hi - lo))
     return cl
+
+
+def finite_difference_atoms(row_ptr: np.ndarray, per_group: int = 16):
+    """The atoms whose forces are checked by finite differences: the `per_group` atoms of
+    lowest coordination (fewest stored blocks in their block row, ties by atom index) and
+    the first `per_group` atoms of full coordination, by atom index."""
+    coord = np.diff(np.asarray(row_ptr))
+    n_at = coord.size
+    low = np.lexsort((np.arange(n_at), coord))[:per_group]
+    bulk = np.nonzero(coord == coord.max())[0][:per_group]
+    return low.astype(np.int64), bulk.astype(np.int64)
