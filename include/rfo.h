@@ -286,9 +286,14 @@ int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
  *   RFO_TUNE_CPLX_PPL, RFO_TUNE_CPLX_ROWS, RFO_TUNE_CPLX_GRID  probes per lane (1, 2), rows
  *                           (1x1: 4, 8) or blocks (9x9: 1, 2) per chunk, and workgroups of
  *                           the complex shifted product of the rational estimate
+ *   RFO_TUNE_ADJOINT_BYTES  memory budget (bytes) of rfo_energy_and_dEdH's vector slots
+ *                           (default: 85% of the device memory free at the call plus what
+ *                           the slots already hold); above it the probe columns run in
+ *                           batches, each adding its sums to the gradient
  * Geometry changes only the order of FP64 sums (rounding).  The segment gradient's step
- * groups and its matrix-core switch change how G is summed and so its rounding (and, for
- * RFO_TUNE_SDDMM_MFMA = 0, which operands the BF16 gradient reads).
+ * groups, its matrix-core switch and the adjoint's probe batches change how G is summed
+ * and so its rounding (and, for RFO_TUNE_SDDMM_MFMA = 0, which operands the BF16
+ * gradient reads).
  * Errors: RFO_E_INVALID for an unknown key or a value out of range. */
 typedef enum {
   RFO_TUNE_PPL = 0,
@@ -304,7 +309,8 @@ typedef enum {
   RFO_TUNE_CPLX_PPL = 10,
   RFO_TUNE_CPLX_ROWS = 11,
   RFO_TUNE_CPLX_GRID = 12,
-  RFO_TUNE_COUNT = 13
+  RFO_TUNE_ADJOINT_BYTES = 13,
+  RFO_TUNE_COUNT = 14
 } rfo_tuning;
 int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value);
 

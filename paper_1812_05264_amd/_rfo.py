@@ -67,10 +67,10 @@ def load():
     lib.rfo_rational_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     for f in (
         "rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
-        "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces", "rfo_set_timing", "rfo_step_timing",
-        "rfo_set_moment_doubling", "rfo_set_tuning", "rfo_traces_at", "rfo_set_overlap",
-        "rfo_get_density_q", "rfo_density_forces", "rfo_cg_stats", "rfo_rational_fit",
-        "rfo_rational_estimate", "rfo_rational_stats"):
+        "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces",
+        "rfo_set_timing", "rfo_step_timing", "rfo_set_moment_doubling", "rfo_set_tuning",
+        "rfo_traces_at", "rfo_set_overlap", "rfo_get_density_q", "rfo_density_forces",
+        "rfo_cg_stats", "rfo_rational_fit", "rfo_rational_estimate", "rfo_rational_stats"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -298,7 +298,7 @@ class Engine:
 
     TUNING = {"ppl": 0, "rpi": 1, "rows_per_wg": 2, "grid": 3, "bf16_chunks": 4, "sddmm_ppl": 5,
               "sddmm_mfma": 6, "sddmm_steps": 7, "sddmm_steps_bf16": 8, "overlap": 9,
-              "cplx_ppl": 10, "cplx_rows": 11, "cplx_grid": 12}
+              "cplx_ppl": 10, "cplx_rows": 11, "cplx_grid": 12, "adjoint_bytes": 13}
 
     def set_tuning(self, key, value=-1):
         """Launch geometry / schedule of this context (rfo_set_tuning); -1 restores the default."""

@@ -15,10 +15,8 @@ namespace {
 //   dF~/dH_hat = z_1 y_0^T + 2 sum_{j=1}^{K-1} z_{j+1} y_j^T,
 // symmetrized (the doubled form is a function of H_hat^T as well as H_hat; the
 // gradient of F~ on symmetric matrices is the symmetric part).
-int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_out,
-                         double *dFdH_out) {
+int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, size_t *n_events_out) {
   const int kp = kernel_precision(ctx);
-  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
   const int64_t K = p / 2;
   int64_t m = 2;
   while (m * m < K) ++m;
@@ -54,11 +52,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   ck.m = m;
   ck.Q = Q;
   ck.store = &ckview;
-  size_t n_events = 0;
-  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, &n_events, true));
-  double *obs = P<double>(ctx->small);
-  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
-                            ctx->sp, obs, ctx->stream));
+  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, n_events_out, true));
   // source weights from beta^g (host copy of the device coefficients)
   std::vector<double> beta((size_t)p);
   HIPCHK(hipMemcpyAsync(beta.data(), P<double>(ctx->coef) + 2 * p, p * sizeof(double),
@@ -172,7 +166,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
     sd.first = 1.0;
     sd.rest = 2.0;
     sd.G = P<double>(ctx->G);
-    sd.accumulate = (q == Q - 1) ? 0 : 1;
+    sd.accumulate = (q == Q - 1 && !g_acc) ? 0 : 1;
     sd.nzlist = P<int64_t>(ctx->nz_up);
     sd.nlist = ctx->n_up;
     sd.ppl = sddmm_ppl(ctx);
@@ -227,40 +221,16 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, double *NEF_ou
   }
   for (int set = 0; set < 2; ++set)
     if (sd_pending[set]) HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_sd[set], 0));
-  HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
-                            P<double>(ctx->G), ctx->stream));
-  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
-  TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
-  TRY(check_flags_and_finish(ctx, n_events));
-  ctx->has_grad = true;
-  ctx->has_dens = false;
-  ctx->mom_p = p;
   return RFO_OK;
 }
 
-}  // namespace
-
-extern "C" {
-int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double *NEF_out,
-                        double *dFdH_out) {
-  if (!ctx) return RFO_E_INVALID;
-  ctx->err.clear();
-  Plan pl;
-  TRY(prepare_call(ctx, T, mu, n_terms, pl));
-  const int64_t p = n_terms;
-  if (ctx->has_s)
-    return fail(ctx, RFO_E_UNSUPPORTED,
-                "the free-energy gradient with an overlap is not implemented; use the density "
-                "blocks and rfo_density_forces");
-  if (ctx->doubling && p >= 2) {
-    TRY(ensure(ctx, ctx->G, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
-    ctx->has_grad = false;
-    return energy_grad_doubling(ctx, pl, p, NEF_out, dFdH_out);
-  }
+// Free energy and gradient by the direct reverse recurrence of r . y_k over p - 1
+// steps: z_{p-1} = beta_{p-1} r, z_{p-2} = 2 H_hat z_{p-1} + beta_{p-2} r,
+// z_i = 2 H_hat z_{i+1} - z_{i+2} + beta_i r, dF~/dH_hat = sum_j c_j z_{j+1} y_j^T
+// (c_0 = 1, c_j = 2) on the blocks on and above the diagonal.
+int energy_grad_direct(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, size_t *n_events_out) {
   const int kp = kernel_precision(ctx);
   const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
-  TRY(ensure(ctx, ctx->G, gbytes));
-  ctx->has_grad = false;
   const int64_t P1 = p - 1;  // gradient terms use y_j, j = 0 .. p-2
   int64_t m = 2;
   while (m * m < P1) ++m;
@@ -278,14 +248,10 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   ck.m = m;
   ck.Q = Q;
   ck.store = &ckview;
-  size_t n_events = 0;
-  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, &n_events));
-  double *obs = P<double>(ctx->small);
-  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
-                            ctx->sp, obs, ctx->stream));
+  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, n_events_out));
 
   if (P1 == 0) {
-    HIPCHK(hipMemsetAsync(ctx->G.p, 0, gbytes, ctx->stream));
+    if (!g_acc) HIPCHK(hipMemsetAsync(ctx->G.p, 0, gbytes, ctx->stream));
   } else {
     const size_t vb = pl.slot_bytes;
     auto ys = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, t); };
@@ -366,7 +332,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       a.first = 1.0;
       a.rest = 2.0;
       a.G = P<double>(ctx->G);
-      a.accumulate = (q == Q - 1) ? 0 : 1;
+      a.accumulate = (q == Q - 1 && !g_acc) ? 0 : 1;
       // the full gradient is symmetric: blocks on and above the diagonal only
       a.nzlist = P<int64_t>(ctx->nz_up);
       a.nlist = ctx->n_up;
@@ -379,12 +345,166 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       }
     }
   }
-  if (P1 > 0)
-    HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
-                              P<double>(ctx->G), ctx->stream));
+  return RFO_OK;
+}
+
+// Bytes of the adjoint's vector slots for the current probes (doubled or direct
+// form; see the two functions above).
+size_t adjoint_slot_bytes(const rfo_ctx *ctx, const Plan &pl, int64_t p, bool dbl) {
+  const int64_t K = dbl ? p / 2 : p - 1;
+  int64_t m = 2;
+  while (m * m < K) ++m;
+  const int64_t Q = K > 0 ? (K + m - 1) / m : 0;
+  const int64_t n_ck = Q > 1 ? 2 * (Q - 1) : 0;
+  const int n_sets = dbl && Q > 1 && tuned(ctx, RFO_TUNE_OVERLAP, 0) != 0 ? 2 : 1;
+  const int64_t slots = dbl ? n_sets * 2 * (m + 2) + n_ck : m + (m + 2) + n_ck;
+  return (size_t)std::max<int64_t>(slots, 2) * pl.slot_bytes;
+}
+
+// Padded width of a probe batch of s_real probes (the rule of rfo_set_probes).
+int padded_probes(int64_t s_real) { return s_real <= 64 ? 64 : (int)((s_real + 127) / 128 * 128); }
+
+// The probe state of a context, swapped for one batch of its probe columns and
+// restored afterwards.
+struct ProbeState {
+  DevBuf sgn, rden, w;
+  int64_t s;
+  int sp;
+  double w_uniform;
+};
+
+}  // namespace
+
+extern "C" {
+int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double *NEF_out,
+                        double *dFdH_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  Plan pl;
+  TRY(prepare_call(ctx, T, mu, n_terms, pl));
+  const int64_t p = n_terms;
+  if (ctx->has_s)
+    return fail(ctx, RFO_E_UNSUPPORTED,
+                "the free-energy gradient with an overlap is not implemented; use the density "
+                "blocks and rfo_density_forces");
+  const bool dbl = ctx->doubling && p >= 2;
+  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
+  TRY(ensure(ctx, ctx->G, gbytes));
+  ctx->has_grad = false;
+  // Probe batches: the vector slots grow with the probe count, so when they would
+  // exceed the memory budget (RFO_TUNE_ADJOINT_BYTES, default 85% of the device
+  // memory free at the call plus what the slots already hold) the probe columns
+  // are processed in batches of the widest padded width that fits, each adding
+  // its sums to G (fixed batch order: bitwise reproducible).
+  size_t budget = 0;
+  {
+    size_t free_b = 0, total_b = 0;
+    HIPCHK(hipMemGetInfo(&free_b, &total_b));
+    budget = (size_t)(0.85 * (double)(free_b + ctx->vec.bytes));
+    if (ctx->tune[RFO_TUNE_ADJOINT_BYTES] >= 0) budget = (size_t)ctx->tune[RFO_TUNE_ADJOINT_BYTES];
+  }
+  const size_t per_probe = adjoint_slot_bytes(ctx, pl, p, dbl) / (size_t)ctx->sp;
+  int width = ctx->sp;
+  while (width > 64 && (size_t)width * per_probe > budget) width = width > 128 ? width - 128 : 64;
+  if ((size_t)width * per_probe > budget)
+    return fail(ctx, RFO_E_NOMEM, "the adjoint needs %zu bytes of vectors for one batch of 64 probes; "
+                "the budget is %zu", (size_t)64 * per_probe, budget);
+  double *obs = P<double>(ctx->small);
+  if (width >= ctx->sp) {
+    TRY(ensure(ctx, ctx->vec, adjoint_slot_bytes(ctx, pl, p, dbl)));
+    size_t n_events = 0;
+    TRY(dbl ? energy_grad_doubling(ctx, pl, p, false, &n_events)
+            : energy_grad_direct(ctx, pl, p, false, &n_events));
+    HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
+                              ctx->sp, obs, ctx->stream));
+    TRY(check_flags_and_finish(ctx, n_events));
+  } else {
+    // batches of `width` padded columns; the moments of every batch are gathered into
+    // the context's [p][sp] moments for the traces (and rfo_traces_at)
+    ProbeState all{ctx->sgn, ctx->rden, ctx->w, ctx->s, ctx->sp, ctx->w_uniform};
+    struct Restore {
+      rfo_ctx *c;
+      const ProbeState &st;
+      DevBuf *bsgn, *brden, *bw;
+      ~Restore() {
+        for (DevBuf *b : {bsgn, brden, bw}) release(*b);
+        c->sgn = st.sgn;
+        c->rden = st.rden;
+        c->w = st.w;
+        c->s = st.s;
+        c->sp = st.sp;
+        c->w_uniform = st.w_uniform;
+      }
+    };
+    DevBuf bsgn, brden, bw, mom_all;
+    Restore restore{ctx, all, &bsgn, &brden, &bw};
+    std::vector<double> w_h((size_t)all.sp);
+    HIPCHK(hipMemcpy(w_h.data(), all.w.p, w_h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    TRY(ensure(ctx, mom_all, (size_t)p * all.sp * sizeof(double)));
+    HIPCHK(hipMemsetAsync(mom_all.p, 0, (size_t)p * all.sp * sizeof(double), ctx->stream));
+    const size_t n = (size_t)ctx->n;
+    bool first = true;
+    for (int64_t c0 = 0; c0 < all.s; c0 += width) {
+      const int64_t s_b = std::min<int64_t>(width, all.s - c0);
+      const int sp_b = padded_probes(s_b);
+      TRY(ensure(ctx, bw, (size_t)sp_b * sizeof(double)));
+      std::vector<double> wb((size_t)sp_b, 0.0);
+      for (int64_t c = 0; c < s_b; ++c) wb[c] = w_h[c0 + c];
+      HIPCHK(hipMemcpy(bw.p, wb.data(), wb.size() * sizeof(double), hipMemcpyHostToDevice));
+      if (all.sgn.p && !all.rden.p) {
+        // sign words [n][sp/64]: c0 is a multiple of 64, so a batch is whole words
+        TRY(ensure(ctx, bsgn, n * (sp_b / 64) * sizeof(uint64_t)));
+        HIPCHK(hipMemsetAsync(bsgn.p, 0, n * (sp_b / 64) * sizeof(uint64_t), ctx->stream));
+        const size_t words = (size_t)(s_b + 63) / 64;
+        HIPCHK(hipMemcpy2DAsync(bsgn.p, (sp_b / 64) * sizeof(uint64_t),
+                                P<uint64_t>(all.sgn) + c0 / 64, (all.sp / 64) * sizeof(uint64_t),
+                                words * sizeof(uint64_t), n, hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->sgn = bsgn;
+        ctx->rden = DevBuf{};
+      } else {
+        TRY(ensure(ctx, brden, n * sp_b * sizeof(double)));
+        HIPCHK(hipMemsetAsync(brden.p, 0, n * sp_b * sizeof(double), ctx->stream));
+        HIPCHK(hipMemcpy2DAsync(brden.p, sp_b * sizeof(double), P<double>(all.rden) + c0,
+                                all.sp * sizeof(double), s_b * sizeof(double), n,
+                                hipMemcpyDeviceToDevice, ctx->stream));
+        ctx->rden = brden;
+        ctx->sgn = DevBuf{};
+      }
+      ctx->w = bw;
+      ctx->s = s_b;
+      ctx->sp = sp_b;
+      ctx->w_uniform = wb[0];
+      for (int64_t c = 1; c < s_b; ++c)
+        if (wb[c] != wb[0]) ctx->w_uniform = 0.0;
+      const Plan bpl = make_plan(ctx);
+      TRY(ensure(ctx, ctx->ring, (size_t)bpl.ring * bpl.grid * sp_b * sizeof(double)));
+      TRY(ensure(ctx, ctx->vec, adjoint_slot_bytes(ctx, bpl, p, dbl)));
+      size_t n_events = 0;
+      TRY(dbl ? energy_grad_doubling(ctx, bpl, p, !first, &n_events)
+              : energy_grad_direct(ctx, bpl, p, !first, &n_events));
+      HIPCHK(hipMemcpy2DAsync(P<double>(mom_all) + c0, all.sp * sizeof(double), ctx->moments.p,
+                              sp_b * sizeof(double), s_b * sizeof(double), p,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+      TRY(check_flags_and_finish(ctx, n_events));
+      first = false;
+    }
+    // the gathered moments (padding columns zero) become the context's moments
+    std::swap(ctx->moments, mom_all);
+    release(mom_all);
+    ctx->sgn = all.sgn;
+    ctx->rden = all.rden;
+    ctx->w = all.w;
+    ctx->s = all.s;
+    ctx->sp = all.sp;
+    ctx->w_uniform = all.w_uniform;
+    HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
+                              ctx->sp, obs, ctx->stream));
+  }
+  HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
+                            P<double>(ctx->G), ctx->stream));
   TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
-  TRY(check_flags_and_finish(ctx, n_events));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->has_grad = true;
   ctx->has_dens = false;
   ctx->mom_p = p;

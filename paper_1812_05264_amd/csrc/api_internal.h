@@ -60,7 +60,7 @@ struct rfo_ctx {
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
   // launch geometry and schedule (rfo_set_tuning); -1 = the measured default
-  int64_t tune[RFO_TUNE_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  int64_t tune[RFO_TUNE_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
   // nonorthogonal basis: overlap S on H's pattern, S^{-1} by conjugate gradients
   bool has_s = false, interval_given = false, has_q = false, has_dens = false;
   double cg_tol = 1e-13;

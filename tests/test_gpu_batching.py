@@ -1,0 +1,87 @@
+"""Probe batching of rfo_energy_and_dEdH: when the adjoint's vector slots (checkpoints,
+replayed y and z vectors) would exceed the memory budget, the probe columns run in
+batches, each adding its sums to the gradient.  Batching changes only the order of the
+FP64 sums: against the unbatched call to 1e-13 and against the oracle at the parity bar,
+for the doubled and the direct recurrence, with Rademacher and dense probes and a ragged
+last batch.  At full size, 1024 probes on the 16,000-atom cluster (over 300 GB unbatched)
+run and equal the sum of four 256-probe calls."""
+
+import re
+
+import numpy as np
+import pytest
+
+from oracle import estimator as est
+from tests.gpu_common import banner, check_blocks, check_rows, engine_or_skip, load_hamiltonian, rel
+from workloads import cu_cluster, rademacher
+from workloads.configs import CONFIGS, build_hamiltonian
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dense", [False, True])
+@pytest.mark.parametrize("doubling", [True, False])
+def test_batched_adjoint_equals_unbatched_and_oracle(doubling, dense):
+    banner(f"batched adjoint doubling={doubling} dense={dense}")
+    cl = cu_cluster(55, config_id=51)
+    H = cl.bsr()
+    s = 200                                   # batches of 64: 64, 64, 64, 8 probes
+    R = rademacher(H.n, s, config_id=901)
+    if dense:
+        R = R * (1.0 + 0.25 * np.cos(np.arange(H.n))[:, None])   # not +-1: stored in FP64
+    w = np.linspace(0.5, 1.5, s) / s
+    T, mu, p = 0.3, 0.2, 121
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H)
+    eng.set_probes(R, w)
+    eng.set_moment_doubling(doubling)
+    whole = eng.energy_and_dEdH(T, mu, p)
+    f_whole = eng.hf_forces(cl.dH_dR())
+    import paper_1812_05264_amd as pkg
+    eng.set_tuning("adjoint_bytes", 1)        # no batch fits: the error names one batch's need
+    with pytest.raises(pkg.RfoError) as err:
+        eng.energy_and_dEdH(T, mu, p)
+    per64 = int(re.search(r"needs (\d+) bytes of vectors for one batch of 64", str(err.value)).group(1))
+    eng.set_tuning("adjoint_bytes", per64 * 3 // 2)   # room for 64 probes, not 128: four batches
+    bat = eng.energy_and_dEdH(T, mu, p)
+    f_bat = eng.hf_forces(cl.dH_dR())
+    again = eng.energy_and_dEdH(T, mu, p)
+    t = eng.traces_at(T, mu)
+    eng.set_tuning("adjoint_bytes", -1)
+    eng.set_moment_doubling(True)
+    assert np.array_equal(bat["dFdH"], again["dFdH"])           # bitwise reproducible
+    for k in ("N", "E", "F"):
+        assert abs(bat[k] - whole[k]) <= 1e-13 * max(1.0, abs(whole[k])), k
+        assert abs(t[k] - whole[k]) <= 1e-13 * max(1.0, abs(whole[k])), k
+    e = rel(bat["dFdH"], whole["dFdH"])
+    print(f"batched vs unbatched G: {e:.2e}")
+    check_blocks(bat["dFdH"], whole["dFdH"], 1e-13, what="batched vs unbatched")
+    o = est.estimate(H, R, T, mu, p, weights=w, gradient=True)
+    check_blocks(bat["dFdH"], o["dFdH"], what="batched vs oracle")
+    check_rows(f_bat, f_whole, 1e-12, what="forces batched vs unbatched")
+
+
+@pytest.mark.timeout(600)
+def test_cu16k_grad_1024_probes_run_in_batches():
+    banner("cu16k_grad, 1024 probes (batched) against four 256-probe calls")
+    cfg = CONFIGS["cu16k_grad"]
+    H, cl = build_hamiltonian(cfg)
+    R = rademacher(H.n, 1024, config_id=cfg.config_id)
+    w = np.full(1024, 1.0 / 1024)
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H)
+    eng.set_probes(R, w)
+    T, mu, p = cfg.T, cfg.mu, cfg.n_terms
+    big = eng.energy_and_dEdH(T, mu, p)
+    f_big = eng.hf_forces(cl.dH_dR())
+    G = np.zeros_like(big["dFdH"])
+    F = 0.0
+    for b in range(4):
+        eng.set_probes(R[:, 256 * b:256 * (b + 1)], w[256 * b:256 * (b + 1)])
+        part = eng.energy_and_dEdH(T, mu, p)
+        G += part["dFdH"]
+        F += part["F"]
+    print(f"1024 probes: F {big['F']:.6f}, sum of four calls {F:.6f}, G rel {rel(big['dFdH'], G):.2e}")
+    assert abs(big["F"] - F) <= 1e-12 * abs(F)
+    check_blocks(big["dFdH"], G, 1e-12, what="1024 probes vs four 256-probe calls")
+    assert np.max(np.abs(f_big.sum(axis=0))) < 1e-9 * np.max(np.abs(f_big))
