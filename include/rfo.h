@@ -138,6 +138,27 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
                       double *moments_out, double *NEF_out,
                       double *density_out);
 
+/* rfo_fermi_moments without density and without any device allocation, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  The same kernels in the same order:
+ * the results equal those of rfo_fermi_moments with density_out = NULL.  The
+ * work memory comes from a fixed device array of the library, 128 MiB per device
+ * (held from the first such call on a device until the process ends), shared by
+ * every call on that device: calls that overlap on one device race.  It must
+ * hold two probe vectors (n * sp * 8 bytes each in FP64; 4 in FP32; 6 in BF16,
+ * sp = s rounded up to 64, or to 128 above 64 probes), the moment partials and
+ * moments, the coefficient tables (about 270 * n_terms bytes) and the moments in
+ * the caller's layout (s * n_terms * 8 bytes).
+ *   moments_out [s][p], NEF_out [3]: as for rfo_fermi_moments (nullable; host
+ *   or device memory).
+ * H and probes are those of the last rfo_set_hamiltonian / rfo_set_probes.
+ * Afterwards rfo_traces_at has no moments (RFO_E_STATE): they stay in the shared
+ * array.
+ * Errors: those of rfo_fermi_moments; RFO_E_INVALID when the work memory would
+ * exceed the array (nothing is launched); RFO_E_UNSUPPORTED with an overlap. */
+int rfo_fermi_moments_noalloc(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
+                              double *moments_out, double *NEF_out);
+
 /* N, E, F at another (T, mu) from the moments of the last rfo_fermi_moments or
  * rfo_energy_and_dEdH call (the moments do not depend on T or mu; only the
  * coefficients are recomputed, paper: Polynomial approximation).  Used for

@@ -52,6 +52,7 @@ def load():
     lib.rfo_set_probes.argtypes = [vp, i64, vp, vp]
     lib.rfo_fermi_moments.argtypes = [vp, dbl, dbl, i64, vp, vp, vp]
     lib.rfo_energy_and_dEdH.argtypes = [vp, dbl, dbl, i64, vp, vp]
+    lib.rfo_fermi_moments_noalloc.argtypes = [vp, dbl, dbl, i64, vp, vp]
     lib.rfo_hf_forces.argtypes = [vp, vp, vp]
     lib.rfo_set_timing.argtypes = [vp, i32]
     lib.rfo_set_moment_doubling.argtypes = [vp, i32]
@@ -67,7 +68,7 @@ def load():
     lib.rfo_rational_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     for f in (
         "rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
-        "rfo_fermi_moments", "rfo_energy_and_dEdH", "rfo_hf_forces",
+        "rfo_fermi_moments", "rfo_fermi_moments_noalloc", "rfo_energy_and_dEdH", "rfo_hf_forces",
         "rfo_set_timing", "rfo_step_timing", "rfo_set_moment_doubling", "rfo_set_tuning",
         "rfo_traces_at", "rfo_set_overlap", "rfo_get_density_q", "rfo_density_forces",
         "rfo_cg_stats", "rfo_rational_fit", "rfo_rational_estimate", "rfo_rational_stats"):
@@ -211,6 +212,16 @@ class Engine:
                                                 _ptr(mom), _ptr(nef), _ptr(dens)))
         return {"N": float(nef[0]), "E": float(nef[1]), "F": float(nef[2]), "moments": mom,
                 "density": dens}
+
+    # -- rfo_fermi_moments_noalloc --------------------------------------------------
+    def fermi_moments_noalloc(self, T, mu, n_terms, moments=True):
+        """The moment-only call without device allocation (library scratch array).
+        Returns dict(N, E, F, moments [s, p] or None)."""
+        mom = np.empty((self.n_probes, int(n_terms))) if moments else None
+        nef = np.empty(3)
+        self._check(self._lib.rfo_fermi_moments_noalloc(self._ctx, float(T), float(mu), int(n_terms),
+                                                        _ptr(mom), _ptr(nef)))
+        return {"N": float(nef[0]), "E": float(nef[1]), "F": float(nef[2]), "moments": mom}
 
     # -- rfo_energy_and_dEdH --------------------------------------------------------
     def energy_and_dEdH(self, T, mu, n_terms, gradient=True, dFdH_out=None):

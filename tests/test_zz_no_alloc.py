@@ -1,0 +1,68 @@
+"""The allocation-free moment call (rfo_fermi_moments_noalloc) against rfo_fermi_moments on
+the same context: identical kernels and order, so the moments and N, E, F must be equal; and
+against the FP64 oracle at the parity bar.  Two calls in a row, the second on a smaller input
+(fewer terms, then a smaller Hamiltonian with fewer probes), so that state left in the shared
+scratch array by the first call cannot leak into the second.  Oversized requests are refused
+before any launch."""
+
+import numpy as np
+import pytest
+
+from oracle import estimator as est
+from tests.gpu_common import banner, check_moments, engine_or_skip, load_hamiltonian
+from workloads import cu_cluster, rademacher, simple_cubic
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(eng, T, mu, p):
+    a = eng.fermi_moments(T, mu, p, moments=True)
+    b = eng.fermi_moments_noalloc(T, mu, p, moments=True)
+    return a, b
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_noalloc_equals_fermi_moments_then_smaller_input(precision):
+    banner(f"noalloc moments {precision}: two calls, second smaller")
+    eng = engine_or_skip()
+    if precision == "bf16":
+        H1, H2 = cu_cluster(201, config_id=41).bsr(), cu_cluster(55, config_id=42).bsr()
+    else:
+        H1, H2 = cu_cluster(201, config_id=41).bsr(), simple_cubic(6, disorder=0.5, config_id=43)
+    cases = [(H1, 200, 0.2, 0.1, 301), (H1, 200, 0.2, 0.1, 120), (H2, 72, 0.3, 0.2, 97)]
+    for dbl in (True, False):
+        eng.set_moment_doubling(dbl)
+        for H, s, T, mu, p in cases:
+            R = rademacher(H.n, s, config_id=700 + s)
+            load_hamiltonian(eng, H, precision=precision)
+            eng.set_probes(R)
+            a, b = _pair(eng, T, mu, p)
+            assert np.array_equal(a["moments"], b["moments"]), (dbl, H.n, p)
+            for k in ("N", "E", "F"):
+                assert a[k] == b[k], (k, dbl, H.n, p)
+            if precision == "fp64":
+                o = est.estimate(H, R, T, mu, p)
+                check_moments(b["moments"], o["moments"], what=f"noalloc n={H.n} p={p}")
+    eng.set_moment_doubling(True)
+
+
+def test_noalloc_refuses_oversized_work_and_repeats():
+    import paper_1812_05264_amd as pkg
+    banner("noalloc: oversized request refused, then a fitting call")
+    eng = engine_or_skip()
+    H = simple_cubic(64)                      # 262,144 sites: 2 x 537 MB of vectors
+    load_hamiltonian(eng, H)
+    eng.set_probes(rademacher(H.n, 256, config_id=9))
+    with pytest.raises(pkg.RfoError, match="allocation-free"):
+        eng.fermi_moments_noalloc(0.1, 0.0, 64)
+    H = simple_cubic(8)
+    R = rademacher(H.n, 64, config_id=0)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    first = eng.fermi_moments_noalloc(0.1, 0.0, 256)
+    second = eng.fermi_moments_noalloc(0.1, 0.0, 256)
+    assert np.array_equal(first["moments"], second["moments"])
+    o = est.estimate(H, R, 0.1, 0.0, 256)
+    check_moments(second["moments"], o["moments"])
+    with pytest.raises(pkg.RfoError):
+        eng.traces_at(0.1, 0.0)              # the moments stay in the shared scratch array
