@@ -311,6 +311,9 @@ int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
  *                           (default: 85% of the device memory free at the call plus what
  *                           the slots already hold); above it the probe columns run in
  *                           batches, each adding its sums to the gradient
+ *   RFO_TUNE_ALT_SWEEP      1 (default): every other Chebyshev-step launch sweeps its rows
+ *                           in the opposite order, so it first reads what the previous
+ *                           launch touched last (0: always forward)
  * Geometry changes only the order of FP64 sums (rounding).  The segment gradient's step
  * groups, its matrix-core switch and the adjoint's probe batches change how G is summed
  * and so its rounding (and, for RFO_TUNE_SDDMM_MFMA = 0, which operands the BF16
@@ -331,7 +334,8 @@ typedef enum {
   RFO_TUNE_CPLX_ROWS = 11,
   RFO_TUNE_CPLX_GRID = 12,
   RFO_TUNE_ADJOINT_BYTES = 13,
-  RFO_TUNE_COUNT = 14
+  RFO_TUNE_ALT_SWEEP = 14,
+  RFO_TUNE_COUNT = 15
 } rfo_tuning;
 int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value);
 

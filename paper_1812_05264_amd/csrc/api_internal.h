@@ -60,7 +60,8 @@ struct rfo_ctx {
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
   // launch geometry and schedule (rfo_set_tuning); -1 = the measured default
-  int64_t tune[RFO_TUNE_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  int64_t tune[RFO_TUNE_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  mutable uint64_t sweeps = 0;  // step launches so far (direction of the alternating sweep)
   // nonorthogonal basis: overlap S on H's pattern, S^{-1} by conjugate gradients
   bool has_s = false, interval_given = false, has_q = false, has_dens = false;
   double cg_tol = 1e-13;
@@ -336,14 +337,16 @@ inline hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::S
   // three accumulator terms need y_{k-1}, which the first pass does not have
   if (a.acc_terms < 0 || a.acc_terms > 3 || (a.acc_terms == 3 && a.c2 == 0.0))
     return hipErrorInvalidValue;
+  rfo::StepArgs b = a;
+  // alternating sweeps: every other launch runs each XCD's range backwards
+  b.reverse = tuned(c, RFO_TUNE_ALT_SWEEP, 1) != 0 ? (int)(c->sweeps++ & 1) : 0;
   if (c->prec == RFO_BF16) {
     // x and out are vector slots; their BF16 copies follow the FP32 vectors
-    rfo::StepArgs b = a;
     b.xb = static_cast<const char *>(a.x) + pl.vec_elems * sizeof(float);
     b.outb = static_cast<char *>(a.out) + pl.vec_elems * sizeof(float);
     return rfo::launch_step_bf16(pl.ntiles, b, c->stream);
   }
-  return rfo::launch_step(c->bd, kernel_precision(c), pl.ppl, a, c->stream);
+  return rfo::launch_step(c->bd, kernel_precision(c), pl.ppl, b, c->stream);
 }
 
 // y = scale r into a vector slot (and its BF16 copy in BF16 mode)
@@ -569,6 +572,7 @@ inline int validate_call(rfo_ctx *ctx, double T, double mu, int64_t p) {
   if (!std::isfinite(mu)) return fail(ctx, RFO_E_INVALID, "mu must be finite");
   if (p < 1 || p > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_terms must be in [1, 2^20]");
   HIPCHK(hipSetDevice(ctx->device));
+  ctx->sweeps = 0;  // every call starts forward: repeated calls sum in the same order
   return RFO_OK;
 }
 

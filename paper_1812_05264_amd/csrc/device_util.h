@@ -23,21 +23,27 @@ __device__ __forceinline__ int xcd_logical(int b, int nwg) {
 // it gathers are still in that XCD's L2.  A workgroup meets the tiles in
 // increasing order, but with a stride above the units per tile it may skip
 // some.
+// With rev set the XCD's range is swept from its end (unit lo + hi - 1 - i): a
+// step that follows one sweeping forward then first reads the rows its
+// predecessor touched last, while the memory-side cache still holds them.
 struct Sched {
-  int64_t i, hi, n_rg;
+  int64_t i, hi, lo, n_rg;
   int stride;
-  __device__ Sched(int n_pt, int64_t n_rg_) : n_rg(n_rg_) {
+  bool rev;
+  __device__ Sched(int n_pt, int64_t n_rg_, bool rev_ = false) : n_rg(n_rg_), rev(rev_) {
     const int b = blockIdx.x, G = gridDim.x;
     const int x = b & 7;
     const int64_t U = (int64_t)n_pt * n_rg;
     stride = G >> 3;
-    i = U * x / 8 + (b >> 3);
+    lo = U * x / 8;
+    i = lo + (b >> 3);
     hi = U * (x + 1) / 8;
   }
   __device__ bool more() const { return i < hi; }
   __device__ void next() { i += stride; }
-  __device__ int pt() const { return (int)(i / n_rg); }
-  __device__ int64_t rg() const { return i - (int64_t)pt() * n_rg; }
+  __device__ int64_t unit() const { return rev ? lo + hi - 1 - i : i; }
+  __device__ int pt() const { return (int)(unit() / n_rg); }
+  __device__ int64_t rg() const { return unit() - (int64_t)pt() * n_rg; }
 };
 
 template <typename T, int N>

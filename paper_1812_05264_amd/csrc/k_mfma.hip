@@ -120,7 +120,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (DBL) flush1(mom2, prow2, pt);
   };
 
-  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+  for (Sched sc(a.n_pt, a.n_rg, a.reverse != 0); sc.more(); sc.next()) {
     const int pt = sc.pt();
     const int64_t rg = sc.rg();
     if (pt != cur_pt) {

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
   if (DBL && mom_on) zero_partials<PPL>(prow2, a.n_pt, wave, lane);
 
-  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+  for (Sched sc(a.n_pt, a.n_rg, a.reverse != 0); sc.more(); sc.next()) {
     const int pt = sc.pt();
     const int64_t rg = sc.rg();
     if (pt != cur_pt) {
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   if (mom_on) zero_partials<PPL>(prow, a.n_pt, wave, lane);
   if (DBL && mom_on) zero_partials<PPL>(prow2, a.n_pt, wave, lane);
 
-  for (Sched sc(a.n_pt, a.n_rg); sc.more(); sc.next()) {
+  for (Sched sc(a.n_pt, a.n_rg, a.reverse != 0); sc.more(); sc.next()) {
     const int pt = sc.pt();
     const int64_t rg = sc.rg();
     if (pt != cur_pt) {

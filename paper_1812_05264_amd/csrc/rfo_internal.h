@@ -56,6 +56,7 @@ struct StepArgs {
   int rpi;                 // 1x1 blocks: rows per wave iteration (1 or 2, 8 neighbours per
                            // chunk) or 7 (one row, 7 neighbours per chunk); 9x9: blocks per chunk
   int grid;                // workgroups (multiple of 8); part has [grid][sp]
+  int reverse;             // sweep each XCD's range of units from its end
 };
 
 // Kernel variant of a step: 1 = density accumulator terms, 2 = doubling
