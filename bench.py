@@ -22,8 +22,9 @@ the whole hot path; each holds chebyshev_steps_per_step = 2047 Chebyshev steps, 
 mean kernel time is roofline.mean_launch_us.
 
   energy_force  energy + gradient + Hellmann-Feynman forces on the 16,000-atom
-                Cu-like cluster (8000 terms, 256 probes), FP64, FP32 and BF16 MFMA
-                with the doubled moments (the library default), and FP64 with the direct
+                Cu-like cluster (8000 terms, 256 probes), FP64, FP32, BF16 MFMA and BF16
+                MFMA with H_hat split into hi + lo BF16 parts (bf16x2), with the doubled
+                moments (the library default), and FP64 with the direct
                 recurrence, with the errors against the FP64 doubled result per atom;
                 and FP64 with a multi-color probe ensemble (one sample, coloring
                 radius 6 A) in place of the 256 Rademacher probes; oracle_gate: per
@@ -32,7 +33,8 @@ mean kernel time is roofline.mean_launch_us.
   overlap       the nonorthogonal basis (S^-1 by conjugate gradients in every step)
                 on the 4,000-atom cluster, 200 terms, moments and P, Q blocks
   cluster_steps Chebyshev step throughput on the Cu-like clusters: cu4k in FP64 (4,000
-                atoms, 4000 terms, 128 probes) and cu16k in BF16 MFMA, FP32 and FP64
+                atoms, 4000 terms, 128 probes) and cu16k in BF16 MFMA (one and two H_hat
+                parts), FP32 and FP64
                 (16,000 atoms, 8000 terms, 256 probes), moments only, with the HBM and
                 arithmetic fractions and the energy errors against FP64 per atom
   copy          a 2 GiB device-to-device copy, timed, as the practical streaming rate
@@ -249,10 +251,10 @@ def energy_force(args):
         # multi-color probe ensemble (one sample, weights 1) at coloring radius ef_colored
         from workloads import rademacher_signs
         colours = pkg.welsh_powell(cl.positions, args.ef_colored)
-        Rc, wc = pkg.colored_probes(colours, 9, rademacher_signs(cl.n_atoms, 9, config_id=cfg.config_id))
+        n_cols = (int(colours.max()) + 1) * 9
         eng = pkg.Engine(0)
         eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, H.e_min, H.e_max, "fp64")
-        eng.set_probes(Rc, wc)
+        eng.set_colored_probes(colours, 9, rademacher_signs(cl.n_atoms, 9, config_id=cfg.config_id))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g = eng.energy_and_dEdH(cfg.T, cfg.mu, n_terms, gradient=False)
@@ -262,13 +264,13 @@ def energy_force(args):
         eng.close()
         del eng
         out["colored"] = {"radius_A": args.ef_colored, "colours": int(colours.max()) + 1,
-                          "probe_columns": int(Rc.shape[1]), "seconds_fp64": round(dt, 4),
+                          "probe_columns": n_cols, "seconds_fp64": round(dt, 4),
                           "F_eV": g["F"]}
         if "fp64" in res:
             _, g64, f64 = res["fp64"]
             out["colored"]["dF_eV_per_atom_vs_rademacher"] = abs(g["F"] - g64["F"]) / cl.n_atoms
             out["colored"]["force_rms_vs_rademacher_eV_per_A"] = float(np.sqrt(np.mean((f - f64) ** 2)))
-        print(f"[bench] energy_force colored r={args.ef_colored} ({Rc.shape[1]} columns): {dt:.3f} s", flush=True)
+        print(f"[bench] energy_force colored r={args.ef_colored} ({n_cols} columns): {dt:.3f} s", flush=True)
     if args.ef_gate and n_terms == cfg.n_terms:
         out["oracle_gate"] = oracle_gate(H, cl, cfg, n_terms, args.ef_precisions.split(","))
     if "fp64" in res:
@@ -364,7 +366,7 @@ def overlap_rational(eng, cl, a, b, eps, T=0.05, mu=1.165):
             "dN_per_atom_rat_vs_poly": abs(g_r["N"] - g_p["N"]) / cl.n_atoms}
 
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x2": 2500.0}
 
 
 def cluster_steps(args):
@@ -408,7 +410,7 @@ def cluster_steps(args):
             eng.set_timing(False)
             eng.close()
             vt = 8 if prec == "fp64" else 4
-            mt = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+            mt = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16x2": 4}[prec]
             b = step_bytes(H, s, vt, mt, density=False)
             flops = 2.0 * 81 * H.nnzb * s
             gbs = b / (ms * 1e-3) / 1e9
@@ -527,7 +529,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=12,
                     help="oracle Chebyshev steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--energy-force", type=int, default=1)
-    ap.add_argument("--ef-precisions", default="fp64,fp32,bf16")
+    ap.add_argument("--ef-precisions", default="fp64,fp32,bf16,bf16x2")
     ap.add_argument("--ef-direct", type=int, default=1,
                     help="also time FP64 energy_force with the direct recurrence (no doubling)")
     ap.add_argument("--ef-gate", type=int, default=1,
@@ -548,7 +550,7 @@ def main():
                     help="run only the energy_force leg (for profiling)")
     ap.add_argument("--sc64-fp32", type=int, default=1,
                     help="also time sc64 with FP32 steps and report its differences (0 = skip)")
-    ap.add_argument("--cluster-configs", default="cu4k=fp64;cu16k=bf16,fp32,fp64",
+    ap.add_argument("--cluster-configs", default="cu4k=fp64;cu16k=bf16,bf16x2,fp32,fp64",
                     help="cluster step legs: config=precisions, separated by ';'")
     ap.add_argument("--cluster-terms", type=int, default=0,
                     help="Chebyshev terms of the cluster step legs (0 = the configuration's)")

@@ -74,8 +74,11 @@ typedef enum {
 typedef enum {
   RFO_FP64 = 0,           /* FP64 vectors and H */
   RFO_FP32 = 1,           /* FP32 vectors and H, FP64 moments */
-  RFO_BF16 = 2            /* BF16 H and vector operands on MFMA, FP32
+  RFO_BF16 = 2,           /* BF16 H and vector operands on MFMA, FP32
                              accumulation and FP32 vectors, FP64 moments */
+  RFO_BF16X2 = 3          /* as RFO_BF16 with H_hat as a pair of BF16 values
+                             hi + lo (two MFMAs per K chunk): the rounding of
+                             H_hat falls from 2^-9 to about 2^-17 relative */
 } rfo_precision;
 
 /* Creates a context on HIP device `device`; `hip_stream` is a hipStream_t or
@@ -220,6 +223,29 @@ int rfo_get_density_q(rfo_ctx *ctx, double *q_out);
  * Errors: RFO_E_STATE without density blocks, or dSdR without Q blocks. */
 int rfo_density_forces(rfo_ctx *ctx, const double *dHdR, const double *dSdR,
                        double *forces_out);
+
+/* Multi-color probe ensemble (paper: Hybrid approximation, the multi-color
+ * vector ensemble; Implementation details, Welsh-Powell coloring).  Host-only:
+ * needs no context and no GPU.  Colours the atoms so that two atoms closer than
+ * r_max (strictly) never share a colour: the atoms are visited in order of
+ * decreasing number of neighbours within r_max (ties by index), each taking the
+ * smallest colour none of its already coloured neighbours holds.
+ *   positions [n_atoms][3] (host), colours_out [n_atoms] (0 .. q-1),
+ *   n_colours_out: q.
+ * Errors: RFO_E_INVALID for n_atoms < 1, r_max <= 0, non-finite input or NULL;
+ * RFO_E_UNSUPPORTED when the cell list would exceed 4e9 cells. */
+int rfo_color_atoms(int64_t n_atoms, const double *positions, double r_max, int32_t *colours_out,
+                    int32_t *n_colours_out);
+
+/* Sets the probes to one sample of the multi-color ensemble, built on the
+ * device: with q = 1 + max colour, column k * n_orb + o (k < q, o < n_orb) holds
+ * signs[a][o] on orbital o of every atom a of colour k (row a * n_orb + o) and
+ * zero elsewhere; every column has weight one.  The orbitals of an atom are
+ * consecutive rows: n_orb must divide the number of rows n.  Replaces
+ * rfo_set_probes with the block it would be given (stored in FP64).
+ *   colours [n / n_orb] (host, >= 0), signs [n / n_orb][n_orb] (host, +-1).
+ * Errors: RFO_E_STATE without a Hamiltonian; RFO_E_INVALID for bad arguments. */
+int rfo_set_colored_probes(rfo_ctx *ctx, const int32_t *colours, int n_orb, const double *signs);
 
 /* Rational (pole) expansion, pole fit (paper: Rational approximation, Eq.
  * rational_fit).  Host-only: needs no context and no GPU.  The paper's fastest

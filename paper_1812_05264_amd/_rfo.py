@@ -15,7 +15,7 @@ import torch  # noqa: F401  (loads the HIP runtime the library will share)
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librfo.so")
 
 RFO_OK = 0
-PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2, "bf16x2": 3}
 STATUS = {0: "RFO_OK", -1: "RFO_E_INVALID", -2: "RFO_E_STATE", -3: "RFO_E_NOMEM",
           -4: "RFO_E_DEVICE", -5: "RFO_E_NUMERIC", -6: "RFO_E_UNSUPPORTED"}
 
@@ -66,12 +66,15 @@ def load():
     lib.rfo_rational_fit.argtypes = [i32, dbl, dbl, dbl, dbl, vp, vp, vp, vp]
     lib.rfo_rational_estimate.argtypes = [vp, dbl, i64, vp, vp, vp, vp, dbl, i64, vp, vp, vp, vp]
     lib.rfo_rational_stats.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.rfo_color_atoms.argtypes = [i64, vp, dbl, vp, ctypes.POINTER(i32)]
+    lib.rfo_set_colored_probes.argtypes = [vp, vp, i32, vp]
     for f in (
         "rfo_create", "rfo_set_hamiltonian", "rfo_get_interval", "rfo_set_probes",
         "rfo_fermi_moments", "rfo_fermi_moments_noalloc", "rfo_energy_and_dEdH", "rfo_hf_forces",
         "rfo_set_timing", "rfo_step_timing", "rfo_set_moment_doubling", "rfo_set_tuning",
         "rfo_traces_at", "rfo_set_overlap", "rfo_get_density_q", "rfo_density_forces",
-        "rfo_cg_stats", "rfo_rational_fit", "rfo_rational_estimate", "rfo_rational_stats"):
+        "rfo_cg_stats", "rfo_rational_fit", "rfo_rational_estimate", "rfo_rational_stats", "rfo_color_atoms",
+        "rfo_set_colored_probes"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -99,6 +102,21 @@ def _host(a, dtype):
 def _complex_pairs(a):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
     return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
+
+
+def color_atoms(positions, r_max):
+    """Welsh-Powell colours [N] (int64) of the atoms for the multi-color probe ensemble
+    (rfo_color_atoms, host-only)."""
+    lib = load()
+    pos = np.ascontiguousarray(positions, dtype=np.float64)
+    if pos.ndim != 2 or pos.shape[1] != 3:
+        raise ValueError("positions must be [N, 3]")
+    out = np.empty(pos.shape[0], dtype=np.int32)
+    q = ctypes.c_int32()
+    rc = lib.rfo_color_atoms(pos.shape[0], _ptr(pos), float(r_max), _ptr(out), ctypes.byref(q))
+    if rc != 0:
+        raise RfoError(rc, "rfo_color_atoms failed")
+    return out.astype(np.int64)
 
 
 def rational_fit(n_nodes, T, mu, e_min, e_max):
@@ -198,6 +216,13 @@ class Engine:
         w = None if weights is None else _host(weights, np.float64)
         self._check(self._lib.rfo_set_probes(self._ctx, int(R.shape[1]), _ptr(R), _ptr(w)))
         self.n_probes = int(R.shape[1])
+
+    def set_colored_probes(self, colours, n_orb, signs):
+        """One sample of the multi-color ensemble, built by the library (weights one)."""
+        col = np.ascontiguousarray(colours, dtype=np.int32)
+        sg = np.ascontiguousarray(signs, dtype=np.float64)
+        self._check(self._lib.rfo_set_colored_probes(self._ctx, _ptr(col), int(n_orb), _ptr(sg)))
+        self.n_probes = (int(col.max()) + 1) * int(n_orb)
 
     # -- rfo_fermi_moments ----------------------------------------------------------
     def fermi_moments(self, T, mu, n_terms, moments=True, density=False, density_out=None):

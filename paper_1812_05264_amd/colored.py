@@ -7,47 +7,21 @@ give q * n_orb probe columns.  Column (k, o) has a random sign on orbital o of
 every atom of colour k and zeros elsewhere.  With one such sample (weights 1)
 the trace estimate sum_c r_c^T X r_c equals tr X plus the same-colour,
 same-orbital off-diagonal elements X_ij r_i r_j, whose atoms lie beyond the
-coloring radius where the density matrix has decayed.  The probes feed the
-library's probe input unchanged (Engine.set_probes with weights of one).
+coloring radius where the density matrix has decayed.  The coloring and the
+probe block are built by the library (rfo_color_atoms, rfo_set_colored_probes);
+colored_probes builds the same block on the host, for the oracle and tests.
 """
 
 import numpy as np
 
 
-def neighbour_lists(positions, r_max):
-    """CSR lists (ptr, idx) of the atoms within distance < r_max of each atom."""
-    from scipy.spatial import cKDTree
-    pos = np.asarray(positions, dtype=np.float64)
-    n = pos.shape[0]
-    pairs = cKDTree(pos).query_pairs(r_max, output_type="ndarray")
-    if pairs.size:
-        d = np.linalg.norm(pos[pairs[:, 0]] - pos[pairs[:, 1]], axis=1)
-        pairs = pairs[d < r_max]                  # strict: at distance r_max no edge
-    i = np.concatenate([pairs[:, 0], pairs[:, 1]]) if pairs.size else np.zeros(0, np.int64)
-    j = np.concatenate([pairs[:, 1], pairs[:, 0]]) if pairs.size else np.zeros(0, np.int64)
-    order = np.lexsort((j, i))
-    i, j = i[order], j[order]
-    ptr = np.zeros(n + 1, dtype=np.int64)
-    np.add.at(ptr, i + 1, 1)
-    return np.cumsum(ptr), j.astype(np.int64)
-
-
 def welsh_powell(positions, r_max):
-    """Colours [N] (0 .. q-1) of the atoms: vertices in order of decreasing
-    degree (ties by index) take the smallest colour not used by an already
-    coloured neighbour."""
-    ptr, idx = neighbour_lists(positions, r_max)
-    n = ptr.shape[0] - 1
-    deg = np.diff(ptr)
-    order = np.lexsort((np.arange(n), -deg))
-    colours = np.full(n, -1, dtype=np.int64)
-    for a in order:
-        used = colours[idx[ptr[a]:ptr[a + 1]]]
-        used = used[used >= 0]
-        taken = np.zeros(used.size + 1, dtype=bool)
-        taken[used[used <= used.size]] = True
-        colours[a] = int(np.argmin(taken))           # first free colour
-    return colours
+    """Colours [N] (0 .. q-1) of the atoms from the library (rfo_color_atoms): no two
+    atoms closer than r_max share a colour; vertices in order of decreasing degree
+    (ties by index) take the smallest colour not used by an already coloured
+    neighbour."""
+    from ._rfo import color_atoms
+    return color_atoms(positions, r_max)
 
 
 def colored_probes(colours, n_orb, signs):

@@ -67,9 +67,9 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     return fail(ctx, RFO_E_INVALID, "block_dim must be 1 or 9 (got %d)", block_dim);
   if (n_block_rows < 1 || n_block_rows > ((int64_t)1 << 30))
     return fail(ctx, RFO_E_INVALID, "n_block_rows out of range");
-  if (precision != RFO_FP64 && precision != RFO_FP32 && precision != RFO_BF16)
+  if (precision != RFO_FP64 && precision != RFO_FP32 && !is_bf16(precision))
     return fail(ctx, RFO_E_INVALID, "unknown precision %d", precision);
-  if (precision == RFO_BF16 && block_dim != 9)
+  if (is_bf16(precision) && block_dim != 9)
     return fail(ctx, RFO_E_UNSUPPORTED, "BF16 MFMA steps need 9x9 blocks");
   if (!values) return fail(ctx, RFO_E_INVALID, "values is NULL");
   if (!std::isfinite(e_min) || !std::isfinite(e_max))
@@ -169,7 +169,7 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     TRY(ensure(ctx, ctx->h32, (nval + npad) * sizeof(float)));
     HIPCHK(hipMemsetAsync(P<float>(ctx->h32) + nval, 0, npad * sizeof(float), ctx->stream));
   }
-  if (precision == RFO_BF16) {
+  if (is_bf16(precision)) {
     // K chunks: block row I's blocks concatenated along K (9 rows each), cut into
     // chunks of 16 K rows; K row k of the row is column c = k % 9 of block
     // nz = row_ptr[I] + k / 9
@@ -192,7 +192,7 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
     TRY(ensure(ctx, ctx->kc_ptr, kp.size() * sizeof(int64_t)));
     TRY(ensure(ctx, ctx->kc_idx, nq * 16 * sizeof(int32_t)));
     TRY(ensure(ctx, ctx->kc_src, nq * 16 * sizeof(int32_t)));
-    TRY(ensure(ctx, ctx->hbf16, nq * 36 * 8));
+    TRY(ensure(ctx, ctx->hbf16, nq * 36 * (precision == RFO_BF16X2 ? 16 : 8)));
     HIPCHK(hipMemcpyAsync(ctx->kc_ptr.p, kp.data(), kp.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                           ctx->stream));
     if (nch > 0) {
@@ -236,15 +236,15 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
                          P<int64_t>(ctx->tpos), ctx->nnzb, ctx->bd, e_min, e_max,
                          P<double>(ctx->h64), precision == RFO_FP32 ? P<float>(ctx->h32) : nullptr,
                          P<int>(ctx->flags), ctx->stream));
-  if (precision == RFO_BF16)
+  if (is_bf16(precision))
     HIPCHK(rfo::launch_pack_bf16(P<double>(ctx->h64), P<int32_t>(ctx->kc_src), ctx->n_chunks,
-                                 ctx->hbf16.p, ctx->stream));
+                                 precision == RFO_BF16X2 ? 1 : 0, ctx->hbf16.p, ctx->stream));
   HIPCHK(hipMemcpyAsync(ctx->flags_h, ctx->flags.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   if (*ctx->flags_h & 1) return fail(ctx, RFO_E_NUMERIC, "non-finite Hamiltonian values");
   if (*ctx->flags_h & 2) return fail(ctx, RFO_E_INVALID, "Hamiltonian values are not symmetric (H_JI != H_IJ^T)");
   ctx->has_up_grp = false;
-  if (block_dim == 9 && precision == RFO_BF16) {
+  if (block_dim == 9 && is_bf16(precision)) {
     // groups of the upper blocks (J >= I, in the order of the upper-block list)
     const int gb = rfo::kSddmmGroup;
     const std::vector<int64_t> &rp = ctx->row_ptr_h;

@@ -159,6 +159,9 @@ inline void release(DevBuf &b) {
   b.bytes = 0;
 }
 
+// BF16 MFMA steps (H_hat in one BF16 part, or split into hi + lo)
+inline bool is_bf16(int prec) { return prec == RFO_BF16 || prec == RFO_BF16X2; }
+
 // a tuning value of the context, or def when it is at its default
 inline int64_t tuned(const rfo_ctx *c, int key, int64_t def) {
   return c->tune[key] >= 0 ? c->tune[key] : def;
@@ -218,14 +221,14 @@ inline Plan make_plan(const rfo_ctx *c) {
   pl.n_pt_step = pl.n_pt;
   pl.ntiles = 0;
   int occ = 1;
-  if (c->prec == RFO_BF16) {
+  if (is_bf16(c->prec)) {
     // 4 MFMA column tiles (64 probes) per wave, 2 blocks per chunk: measured best
     // (wider tiles or chunks cost more registers than the loads they add in flight)
     pl.ntiles = 4;
     pl.rpi = 2;
     pl.n_pt_step = c->sp / (16 * pl.ntiles);
     pl.rpi = (int)tuned(c, RFO_TUNE_BF16_CHUNKS, pl.rpi);
-    occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi));
+    occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi, c->prec == RFO_BF16X2 ? 1 : 0));
   } else {
     occ = std::max(1, rfo::step_blocks_per_cu(c->bd, c->prec == RFO_FP64 ? 0 : 1, pl.ppl, pl.rpi));
   }
@@ -239,7 +242,7 @@ inline Plan make_plan(const rfo_ctx *c) {
   grid = std::max<int64_t>(8, grid / 8 * 8);
   pl.grid = (int)grid;
   pl.vec_elems = (size_t)c->n * (size_t)c->sp;
-  pl.slot_bytes = pl.vec_elems * (pl.vt_bytes + (c->prec == RFO_BF16 ? 2 : 0));
+  pl.slot_bytes = pl.vec_elems * (pl.vt_bytes + (is_bf16(c->prec) ? 2 : 0));
   return pl;
 }
 
@@ -248,9 +251,10 @@ inline void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
   a.row_ptr = P<int64_t>(c->row_ptr);
   a.col = P<int32_t>(c->col);
   a.hval = c->prec == RFO_FP64 ? c->h64.p : (c->prec == RFO_FP32 ? c->h32.p : c->hbf16.p);
-  if (c->prec == RFO_BF16) {
+  if (is_bf16(c->prec)) {
     a.kc_ptr = P<int64_t>(c->kc_ptr);
     a.kc_idx = P<int32_t>(c->kc_idx);
+    a.hsplit = c->prec == RFO_BF16X2 ? 1 : 0;
   }
   a.sgn = c->signs ? P<uint64_t>(c->sgn) : nullptr;
   a.rden = c->signs ? nullptr : P<double>(c->rden);
@@ -284,7 +288,7 @@ inline int kernel_precision(const rfo_ctx *c) { return c->prec == RFO_FP64 ? 0 :
 // contraction).  FP32 steps keep the VALU contraction: an FP32-MFMA version
 // measured no faster at full size and sums in FP32.
 inline bool use_mfma_sddmm(const rfo_ctx *c) {
-  if (c->bd != 9 || c->prec != RFO_BF16 || c->w_uniform == 0.0 || !c->has_up_grp) return false;
+  if (c->bd != 9 || !is_bf16(c->prec) || c->w_uniform == 0.0 || !c->has_up_grp) return false;
   if (c->sp % 32 != 0) return false;
   return tuned(c, RFO_TUNE_SDDMM_MFMA, 1) != 0;
 }
@@ -340,7 +344,7 @@ inline hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::S
   rfo::StepArgs b = a;
   // alternating sweeps: every other launch runs each XCD's range backwards
   b.reverse = tuned(c, RFO_TUNE_ALT_SWEEP, 1) != 0 ? (int)(c->sweeps++ & 1) : 0;
-  if (c->prec == RFO_BF16) {
+  if (is_bf16(c->prec)) {
     // x and out are vector slots; their BF16 copies follow the FP32 vectors
     b.xb = static_cast<const char *>(a.x) + pl.vec_elems * sizeof(float);
     b.outb = static_cast<char *>(a.out) + pl.vec_elems * sizeof(float);
@@ -351,7 +355,7 @@ inline hipError_t launch_any_step(const rfo_ctx *c, const Plan &pl, const rfo::S
 
 // y = scale r into a vector slot (and its BF16 copy in BF16 mode)
 inline hipError_t launch_init_slot(const rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {
-  a.outb = c->prec == RFO_BF16 ? static_cast<char *>(a.out) + pl.vec_elems * sizeof(float) : nullptr;
+  a.outb = is_bf16(c->prec) ? static_cast<char *>(a.out) + pl.vec_elems * sizeof(float) : nullptr;
   return rfo::launch_init(kernel_precision(c), a, c->stream);
 }
 

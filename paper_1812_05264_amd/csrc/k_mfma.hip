@@ -39,7 +39,7 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 // Occupancy 4 (at most 128 registers) is part of the design: the step is bound by
 // the gathers each wave keeps in flight, and at occupancy 3 the same kernel is
 // much slower.
-template <int NT, int U, bool NTH, int MODE>
+template <int NT, int U, bool NTH, int MODE, bool SPLIT>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_step9_bf16(
     StepArgs a) {
   constexpr int TW = 16 * NT;  // probes per wave (tile width)
@@ -55,6 +55,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   unsigned short *outb = static_cast<unsigned short *>(a.outb);
   float *acc = static_cast<float *>(a.acc);
   const uint2 *hpack = static_cast<const uint2 *>(a.hval);
+  // SPLIT: each pack entry holds the high and the low BF16 parts of its four values
+  const uint4 *hpack2 = static_cast<const uint4 *>(a.hval);
   const i4 *kidx = reinterpret_cast<const i4 *>(a.kc_idx);
   const bool has_prev = a.c2 != 0.0;
   const bool add_r = a.beta != nullptr;
@@ -136,17 +138,28 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int t = 0; t < NT; ++t) d[t] = f4{0.f, 0.f, 0.f, 0.f};
       const int64_t q0 = sld(a.kc_ptr + I), q1 = sld(a.kc_ptr + I + 1);
       for (int64_t qc = q0; qc < q1; qc += U) {
-        s4 av[U];
+        s4 av[U], avl[U];
         VecN<unsigned short, NT> xr[U][4];
         const bool a_live = n < 9;
         const int a_idx = a_live ? g * 9 + n : 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t q = min(qc + u, q1 - 1);  // a repeated chunk is not accumulated
-          const uint2 p = hpack[q * 36 + a_idx];
+          uint2 p, pl;
+          if constexpr (SPLIT) {
+            const uint4 p4 = hpack2[q * 36 + a_idx];
+            p = make_uint2(p4.x, p4.y);
+            pl = make_uint2(p4.z, p4.w);
+          } else {
+            p = hpack[q * 36 + a_idx];
+          }
           av[u] = a_live ? s4{(short)(p.x & 0xffff), (short)(p.x >> 16), (short)(p.y & 0xffff),
                               (short)(p.y >> 16)}
                          : s4{0, 0, 0, 0};
+          if constexpr (SPLIT)
+            avl[u] = a_live ? s4{(short)(pl.x & 0xffff), (short)(pl.x >> 16), (short)(pl.y & 0xffff),
+                                 (short)(pl.y >> 16)}
+                            : s4{0, 0, 0, 0};
           // the chunk's 16 source rows (wave-uniform), four per lane group
           const i4 k0 = sld(kidx + q * 4), k1 = sld(kidx + q * 4 + 1);
           const i4 k2 = sld(kidx + q * 4 + 2), k3 = sld(kidx + q * 4 + 3);
@@ -169,6 +182,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
             for (int t = 0; t < NT; ++t) {
               const s4 bv = s4{(short)xr[u][0].v[t], (short)xr[u][1].v[t], (short)xr[u][2].v[t],
                                (short)xr[u][3].v[t]};
+              // the low part first: the two products add in FP32 as (lo + hi) y
+              if constexpr (SPLIT) d[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(avl[u], bv, d[t], 0, 0, 0);
               d[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[u], bv, d[t], 0, 0, 0);
             }
           }
@@ -378,36 +393,49 @@ hipError_t launch_sddmm_bf16(const SddmmMfmaArgs &a, hipStream_t s) {
 }
 
 // Pack H_hat (FP64 [nnzb][9][9]) into the chunked A-operand layout above.
+// With split, entry e holds two uint2: the BF16 values hi = bf16(h) and then
+// lo = bf16(h - hi) (h the FP64 entry; hi + lo carries about 16 significant bits).
 __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hhat,
                                                    const int32_t *__restrict__ kc_src,
-                                                   int64_t n_chunks, uint2 *__restrict__ apack) {
+                                                   int64_t n_chunks, int split,
+                                                   uint2 *__restrict__ apack) {
   const int64_t total = n_chunks * 36;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = e / 36;
     const int r = (int)(e - q * 36);
     const int gg = r / 9, m = r - gg * 9;
-    unsigned short v[4];
+    unsigned short v[4], vl[4];
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
       const int code = kc_src[q * 16 + 4 * gg + kk];
-      const float f = code >= 0 ? (float)hhat[(int64_t)(code / 9) * 81 + m * 9 + code % 9] : 0.f;
-      v[kk] = bf16_bits(f);
+      const double h = code >= 0 ? hhat[(int64_t)(code / 9) * 81 + m * 9 + code % 9] : 0.0;
+      v[kk] = bf16_bits((float)h);
+      const double hi = (double)__builtin_bit_cast(float, (unsigned)v[kk] << 16);
+      vl[kk] = bf16_bits((float)(h - hi));
     }
-    apack[e] = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
-                          (unsigned)v[2] | ((unsigned)v[3] << 16));
+    const uint2 hi2 = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
+                                 (unsigned)v[2] | ((unsigned)v[3] << 16));
+    if (split) {
+      apack[2 * e] = hi2;
+      apack[2 * e + 1] = make_uint2((unsigned)vl[0] | ((unsigned)vl[1] << 16),
+                                    (unsigned)vl[2] | ((unsigned)vl[3] << 16));
+    } else {
+      apack[e] = hi2;
+    }
   }
 }
 
 namespace {
 
-const void *select_bf16(int nt_tiles, int u, int mode) {
+template <bool SPLIT>
+const void *select_bf16_t(int nt_tiles, int u, int mode) {
 #define RFO_BF16_CASE(T, UU)                                                        \
   if (nt_tiles == T && u == UU)                                                     \
-    return mode == 1   ? (const void *)k_step9_bf16<T, UU, true, 1>                 \
-           : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2>                 \
-           : mode == 3 ? (const void *)k_step9_bf16<T, UU, true, 3>                 \
-                       : (const void *)k_step9_bf16<T, UU, true, 0>;
+    return mode == 1   ? (const void *)k_step9_bf16<T, UU, true, 1, SPLIT>          \
+           : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2, SPLIT>          \
+           : mode == 3 ? (const void *)k_step9_bf16<T, UU, true, 3, SPLIT>          \
+                       : (const void *)k_step9_bf16<T, UU, true, 0, SPLIT>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
   RFO_BF16_CASE(4, 4)
@@ -415,10 +443,14 @@ const void *select_bf16(int nt_tiles, int u, int mode) {
   return nullptr;
 }
 
+const void *select_bf16(int nt_tiles, int u, int mode, int split) {
+  return split ? select_bf16_t<true>(nt_tiles, u, mode) : select_bf16_t<false>(nt_tiles, u, mode);
+}
+
 }  // namespace
 
-int step_bf16_blocks_per_cu(int nt_tiles, int u) {
-  const void *f = select_bf16(nt_tiles, u, 0);
+int step_bf16_blocks_per_cu(int nt_tiles, int u, int split) {
+  const void *f = select_bf16(nt_tiles, u, 0, split);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -426,18 +458,18 @@ int step_bf16_blocks_per_cu(int nt_tiles, int u) {
 }
 
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s) {
-  const void *f = select_bf16(nt_tiles, a.rpi, step_mode(a));
+  const void *f = select_bf16(nt_tiles, a.rpi, step_mode(a), a.hsplit);
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);
 }
 
-hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks,
+hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks, int split,
                             void *apack, hipStream_t s) {
   if (n_chunks == 0) return hipSuccess;
   int64_t blocks = (n_chunks * 36 + kWG - 1) / kWG;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(kWG), 0, s, hhat, kc_src, n_chunks,
+  hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(kWG), 0, s, hhat, kc_src, n_chunks, split,
                      static_cast<uint2 *>(apack));
   return hipGetLastError();
 }

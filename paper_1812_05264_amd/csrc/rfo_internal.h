@@ -57,6 +57,7 @@ struct StepArgs {
                            // chunk) or 7 (one row, 7 neighbours per chunk); 9x9: blocks per chunk
   int grid;                // workgroups (multiple of 8); part has [grid][sp]
   int reverse;             // sweep each XCD's range of units from its end
+  int hsplit;              // BF16 steps: the pack holds hi and lo BF16 parts of H_hat
 };
 
 // Kernel variant of a step: 1 = density accumulator terms, 2 = doubling
@@ -94,11 +95,12 @@ int step_blocks_per_cu(int bd, int precision, int ppl, int rpi);
 // BF16 MFMA step for 9x9 blocks; a.hval holds the packed A operands
 // ([nnzb + kStepPad][27] uint2), a.n_pt counts tiles of 16 * nt_tiles probes.
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s);
-int step_bf16_blocks_per_cu(int nt_tiles, int u);  // u = blocks per chunk (a.rpi)
+int step_bf16_blocks_per_cu(int nt_tiles, int u, int split);  // u = blocks per chunk (a.rpi)
 // A operands of the K-packed BF16 step: chunk q, lane group g, output row m holds
 // H_hat[nz][m][c] for the four K rows 4g..4g+3 of the chunk, whose source codes
 // kc_src[16 q + k] = nz * 9 + c (-1: zero) list the block and column of each K row.
-hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks,
+// split: each entry also carries the low BF16 parts bf16(h - bf16(h)).
+hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks, int split,
                             void *apack, hipStream_t s);
 
 // ---------------------------------------------------------------------------

@@ -7,7 +7,7 @@ import numpy as np
 
 from oracle import estimator as est
 from oracle import trunc
-from paper_1812_05264_amd.colored import colored_probes, neighbour_lists, welsh_powell
+from paper_1812_05264_amd.colored import colored_probes, welsh_powell
 from workloads import cu_cluster, rademacher_signs
 
 
@@ -16,12 +16,26 @@ def brute_pairs(pos, r):
     return (d < r) & ~np.eye(len(pos), dtype=bool)
 
 
-def test_neighbour_lists_match_brute_force():
-    pos = cu_cluster(79, config_id=40).positions
-    ptr, idx = neighbour_lists(pos, 5.2)
-    adj = brute_pairs(pos, 5.2)
+def test_library_coloring_on_an_irregular_cloud():
+    """rfo_color_atoms on points off any lattice (many degree ties, atoms exactly at the
+    radius): a proper coloring at distance < r (strict), the greedy rule in the Welsh-Powell
+    order, checked against brute-force distances."""
+    rng = np.random.default_rng(11)
+    pos = rng.uniform(-9.0, 9.0, size=(300, 3))
+    pos[1] = pos[0] + np.array([4.0, 0.0, 0.0])          # exactly at r: no edge
+    r = 4.0
+    c = welsh_powell(pos, r)
+    adj = brute_pairs(pos, r)
+    assert not adj[0, 1]
+    i, j = np.nonzero(adj)
+    assert np.all(c[i] != c[j])
+    deg = adj.sum(axis=1)
+    order = np.lexsort((np.arange(len(pos)), -deg))
+    rank = np.empty(len(pos), dtype=int)
+    rank[order] = np.arange(len(pos))
     for a in range(len(pos)):
-        assert sorted(idx[ptr[a]:ptr[a + 1]].tolist()) == np.nonzero(adj[a])[0].tolist()
+        earlier = {int(c[b]) for b in np.nonzero(adj[a])[0] if rank[b] < rank[a]}
+        assert c[a] == min(set(range(len(earlier) + 1)) - earlier)
 
 
 def test_welsh_powell_is_a_proper_greedy_coloring():

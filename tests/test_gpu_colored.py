@@ -63,3 +63,28 @@ def test_colored_error_is_the_same_colour_sum():
         assert abs(err - np.sum(P * E)) < 1e-9 * np.trace(P), r_max
         errs.append((r_max, R.shape[1], err))
     print("coloring radius, probe columns, N error:", errs)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16"])
+def test_library_built_colored_probes_equal_the_host_block(prec):
+    """rfo_set_colored_probes builds on the device the block colored_probes builds on the
+    host: the same moments, traces and gradient bit for bit."""
+    banner(f"library-built colored probes {prec}")
+    from paper_1812_05264_amd.colored import colored_probes, welsh_powell
+    eng = engine_or_skip()
+    cl = cu_cluster(201, config_id=46)
+    H = cl.bsr()
+    c = welsh_powell(cl.positions, 6.0)
+    signs = rademacher_signs(cl.n_atoms, 9, config_id=46)
+    R, w = colored_probes(c, 9, signs)
+    load_hamiltonian(eng, H, precision=prec)
+    T, mu, p = 0.3, 0.3, 80
+    eng.set_probes(R, w)
+    a = eng.fermi_moments(T, mu, p, moments=True)
+    ga = eng.energy_and_dEdH(T, mu, p)
+    eng.set_colored_probes(c, 9, signs)
+    b = eng.fermi_moments(T, mu, p, moments=True)
+    gb = eng.energy_and_dEdH(T, mu, p)
+    assert np.array_equal(a["moments"], b["moments"])
+    assert a["F"] == b["F"] and ga["F"] == gb["F"]
+    assert np.array_equal(ga["dFdH"], gb["dFdH"])

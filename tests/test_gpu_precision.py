@@ -170,3 +170,42 @@ def test_kept_pattern_with_new_values_and_precisions():
         assert np.array_equal(a["moments"], b["moments"]), prec
         assert np.array_equal(a["density"], b["density"]), prec
         assert np.array_equal(ga["dFdH"], gb["dFdH"]), prec
+
+
+@pytest.mark.parametrize("name,atoms,s,p", [("cu201_s256", 201, 256, 120), ("cu55_s100", 55, 100, 90)])
+def test_bf16x2_split_hamiltonian_against_oracle(name, atoms, s, p):
+    """H_hat as a pair of BF16 values (hi + lo, two MFMAs per K chunk): the same steps with
+    the H_hat rounding removed down to about 2^-17.  What remains is the rounding of the
+    gathered vector operands (random from probe to probe), so the probe-averaged traces
+    come much closer to the oracle than with one BF16 part; the gradient path runs too."""
+    banner(f"bf16x2 {name}")
+    eng = engine_or_skip()
+    cl = cu_cluster(atoms, config_id=23)
+    H = cl.bsr()
+    R = rademacher(H.n, s, config_id=604)
+    T, mu = 0.3, 0.2
+    o = est.estimate(H, R, T, mu, p, density=True)
+    err = {}
+    for prec in ("bf16", "bf16x2"):
+        load_hamiltonian(eng, H, precision=prec)
+        eng.set_probes(R)
+        g = eng.fermi_moments(T, mu, p, density=True)
+        d = eng.fermi_moments(T, mu, p, moments=True)
+        assert np.all(g["moments"][:, 0] == o["moments"][:, 0])
+        err[prec] = {k: abs(g[k] - o[k]) / cl.n_atoms for k in ("N", "E", "F")}
+        err[prec]["moments"] = rel(g["moments"], o["moments"])
+        err[prec]["density"] = rel(g["density"], o["density"])
+        err[prec]["F_doubled"] = abs(d["F"] - o["F"]) / cl.n_atoms
+        e = eng.energy_and_dEdH(T, mu, p)
+        err[prec]["F_adjoint"] = abs(e["F"] - o["F"]) / cl.n_atoms
+        assert np.isfinite(e["dFdH"]).all()
+    print(f"{name}: " + "; ".join(f"{k}: " + ", ".join(f"{q} {v:.1e}" for q, v in e_.items())
+                                  for k, e_ in err.items()))
+    for k in ("moments", "density"):
+        assert err["bf16x2"][k] < 3e-2
+    # with the doubled moments (the moment-only and adjoint default) the free energy
+    # improves many times over: measured 133x (cu201, 256 probes) and 15x (cu55, 100 probes);
+    # the direct recurrence with density gains only 2x (its moments r . y_k weigh the
+    # vector rounding more)
+    for k in ("F_doubled", "F_adjoint"):
+        assert err["bf16x2"][k] < 0.2 * err["bf16"][k], k
