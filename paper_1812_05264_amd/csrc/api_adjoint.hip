@@ -425,9 +425,9 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
     struct Restore {
       rfo_ctx *c;
       const ProbeState &st;
-      DevBuf *bsgn, *brden, *bw;
+      DevBuf *bsgn, *brden, *bw, *bmom;
       ~Restore() {
-        for (DevBuf *b : {bsgn, brden, bw}) release(*b);
+        for (DevBuf *b : {bsgn, brden, bw, bmom}) release(*b);
         c->sgn = st.sgn;
         c->rden = st.rden;
         c->w = st.w;
@@ -437,7 +437,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       }
     };
     DevBuf bsgn, brden, bw, mom_all;
-    Restore restore{ctx, all, &bsgn, &brden, &bw};
+    Restore restore{ctx, all, &bsgn, &brden, &bw, &mom_all};
     std::vector<double> w_h((size_t)all.sp);
     HIPCHK(hipMemcpy(w_h.data(), all.w.p, w_h.size() * sizeof(double), hipMemcpyDeviceToHost));
     TRY(ensure(ctx, mom_all, (size_t)p * all.sp * sizeof(double)));

@@ -144,7 +144,14 @@ int rfo_set_colored_probes(rfo_ctx *ctx, const int32_t *colours, int n_orb, cons
   const size_t n = (size_t)ctx->n;
   TRY(ensure(ctx, ctx->rden, n * sp * sizeof(double)));
   TRY(ensure(ctx, ctx->w, sp * sizeof(double)));
-  DevBuf dcol, dsign;
+  struct Staging {
+    DevBuf col, sign;
+    ~Staging() {
+      release(col);
+      release(sign);
+    }
+  } st;
+  DevBuf &dcol = st.col, &dsign = st.sign;
   TRY(ensure(ctx, dcol, (size_t)n_atoms * sizeof(int32_t)));
   TRY(ensure(ctx, dsign, n * sizeof(double)));
   HIPCHK(hipMemsetAsync(ctx->rden.p, 0, n * sp * sizeof(double), ctx->stream));
@@ -157,8 +164,6 @@ int rfo_set_colored_probes(rfo_ctx *ctx, const int32_t *colours, int n_orb, cons
   for (int64_t c = 0; c < s; ++c) w[(size_t)c] = 1.0;
   HIPCHK(hipMemcpyAsync(ctx->w.p, w.data(), sp * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIPCHK(hipStreamSynchronize(ctx->stream));
-  release(dcol);
-  release(dsign);
   release(ctx->sgn);
   ctx->signs = false;
   ctx->w_uniform = 1.0;

@@ -577,6 +577,7 @@ inline int validate_call(rfo_ctx *ctx, double T, double mu, int64_t p) {
   if (p < 1 || p > (1 << 20)) return fail(ctx, RFO_E_INVALID, "n_terms must be in [1, 2^20]");
   HIPCHK(hipSetDevice(ctx->device));
   ctx->sweeps = 0;  // every call starts forward: repeated calls sum in the same order
+  ctx->mom_p = 0;   // the stored moments are overwritten: valid again only when the call succeeds
   return RFO_OK;
 }
 
