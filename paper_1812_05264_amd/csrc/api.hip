@@ -384,6 +384,7 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
     a.accumulate = 0;
     a.nzlist = nullptr;
     a.ppl = sddmm_ppl(ctx);
+    a.s_live = (int)ctx->s;
     HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
     if (qx) {
       a.xbase = qx;

@@ -170,6 +170,7 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, si
     sd.nzlist = P<int64_t>(ctx->nz_up);
     sd.nlist = ctx->n_up;
     sd.ppl = sddmm_ppl(ctx);
+    sd.s_live = (int)ctx->s;
     sd.sym = 1;
     hipStream_t sd_stream = ctx->stream;
     if (overlap) {
@@ -337,6 +338,7 @@ int energy_grad_direct(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, size
       a.nzlist = P<int64_t>(ctx->nz_up);
       a.nlist = ctx->n_up;
       a.ppl = sddmm_ppl(ctx);
+      a.s_live = (int)ctx->s;
       HIPCHK(launch_sddmm_segment(ctx, kp, a, pl.slot_bytes, ctx->stream));
       if (q > 0) {
         // carries for the segment below: zs[m] = z_{j0+1}, zs[m+1] = z_{j0+2}

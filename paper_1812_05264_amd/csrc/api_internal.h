@@ -60,7 +60,7 @@ struct rfo_ctx {
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
   // launch geometry and schedule (rfo_set_tuning); -1 = the measured default
-  int64_t tune[RFO_TUNE_COUNT] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
+  int64_t tune[RFO_TUNE_COUNT];
   mutable uint64_t sweeps = 0;  // step launches so far (direction of the alternating sweep)
   // nonorthogonal basis: overlap S on H's pattern, S^{-1} by conjugate gradients
   bool has_s = false, interval_given = false, has_q = false, has_dens = false;
@@ -86,6 +86,10 @@ struct rfo_ctx {
   // gradient while the next segment's steps run on `stream`
   hipStream_t side = nullptr;
   hipEvent_t ev_rev = nullptr, ev_sd[2] = {nullptr, nullptr};
+
+  rfo_ctx() {
+    for (int64_t &v : tune) v = -1;  // every key at its default
+  }
 
   ~rfo_ctx() {
     hipSetDevice(device);
@@ -265,6 +269,8 @@ inline void fill_step(rfo_ctx *c, const Plan &pl, rfo::StepArgs &a) {
   a.n_pt = pl.n_pt_step;
   a.rpi = pl.rpi;
   a.grid = pl.grid;
+  // dense probes carry zero padding columns, and so does every vector made from them
+  a.s_live = c->signs ? c->sp : (int)c->s;
 }
 
 inline void fill_init(rfo_ctx *c, const Plan &pl, rfo::InitArgs &a) {

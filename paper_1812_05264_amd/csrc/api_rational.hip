@@ -257,6 +257,7 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   sa.scale = 1.0;
   sa.rest = 1.0;
   sa.ppl = sddmm_ppl(ctx);
+  sa.s_live = (int)ctx->s;
   const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
   ctx->has_grad = ctx->has_dens = ctx->has_q = false;
   if (grad) {

@@ -52,6 +52,14 @@ struct alignas(sizeof(T) * N) VecN {
 };
 
 template <typename T, int N>
+__device__ __forceinline__ VecN<T, N> zerov() {
+  VecN<T, N> r;
+#pragma unroll
+  for (int q = 0; q < N; ++q) r.v[q] = (T)0;
+  return r;
+}
+
+template <typename T, int N>
 __device__ __forceinline__ VecN<T, N> ldv(const T *p) {
   return *reinterpret_cast<const VecN<T, N> *>(p);
 }

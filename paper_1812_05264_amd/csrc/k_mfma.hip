@@ -39,7 +39,7 @@ typedef int i4 __attribute__((ext_vector_type(4)));
 // Occupancy 4 (at most 128 registers) is part of the design: the step is bound by
 // the gathers each wave keeps in flight, and at occupancy 3 the same kernel is
 // much slower.
-template <int NT, int U, bool NTH, int MODE, bool SPLIT>
+template <int NT, int U, bool NTH, int MODE, bool SPLIT, bool PAD>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_step9_bf16(
     StepArgs a) {
   constexpr int TW = 16 * NT;  // probes per wave (tile width)
@@ -48,6 +48,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   const int g = lane >> 4, n = lane & 15;
   const int sp = a.sp;
   const int nw = sp >> 6;
+  const int s_live = a.s_live > 0 ? a.s_live : sp;
   const float *__restrict__ x = static_cast<const float *>(a.x);
   const unsigned short *__restrict__ xb = static_cast<const unsigned short *>(a.xb);
   const float *prev = static_cast<const float *>(a.prev);
@@ -130,6 +131,9 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       cur_pt = pt;
     }
     const int cp = pt * TW + n * NT;  // first probe column of this lane
+    // PAD: a lane whose probes are all zero padding loads nothing (its inputs are
+    // zero); without padding columns the predicate is compiled out
+    const bool live = !PAD || cp < s_live;
     const int64_t r0 = rg * a.rows_per_wg;
     const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
     for (int64_t I = r0 + wave; I < r1; I += kWaves) {
@@ -167,7 +171,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           const int src[4] = {kg.x, kg.y, kg.z, kg.w};
 #pragma unroll
           for (int kk = 0; kk < 4; ++kk) {
-            if (src[kk] >= 0) {
+            if (src[kk] >= 0 && live) {
               xr[u][kk] = ldv<unsigned short, NT>(xb + (int64_t)src[kk] * sp + cp);
             } else {
 #pragma unroll
@@ -197,11 +201,12 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       uint64_t sw4[NPRE];
       auto load_row = [&](int i, int slot) {
         const int64_t row = I * 9 + min(4 * g + i, 8);
-        if (has_prev) pv4[slot] = NTH ? ldv_nt<float, NT>(prev + row * sp + cp)
-                                      : ldv<float, NT>(prev + row * sp + cp);
+        if (has_prev)
+          pv4[slot] = !live ? zerov<float, NT>()
+                            : NTH ? ldv_nt<float, NT>(prev + row * sp + cp) : ldv<float, NT>(prev + row * sp + cp);
         // the row's own FP32 y_k is read once: non-temporal, so that it does not
         // displace the gathered BF16 copies (measured 4% faster)
-        if (m >= 2 || DBL) xs4[slot] = ldv_nt<float, NT>(x + row * sp + cp);
+        if (m >= 2 || DBL) xs4[slot] = live ? ldv_nt<float, NT>(x + row * sp + cp) : zerov<float, NT>();
         if (need_r && a.sgn) sw4[slot] = a.sgn[row * nw + (cp >> 6)];
       };
       if constexpr (NPRE == 4) {
@@ -222,10 +227,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (SRC) {
 #pragma unroll
           for (int t = 0; t < 3; ++t)
-            if (t < nsrc) sv[t] = ldv_nt<float, NT>(srcp[t] + off);
+            if (t < nsrc) sv[t] = live ? ldv_nt<float, NT>(srcp[t] + off) : zerov<float, NT>();
         }
         VecN<double, NT> rv;
-        if (need_r && !a.sgn) rv = ldv<double, NT>(a.rden + off);
+        if (need_r && !a.sgn) rv = live ? ldv<double, NT>(a.rden + off) : zerov<double, NT>();
         VecN<float, NT> o;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
@@ -256,7 +261,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
         for (int t = 0; t < NT; ++t) ob.v[t] = bf16_bits(o.v[t]);
         stv<unsigned short, NT>(outb + off, ob);
         if (m > 0) {
-          VecN<float, NT> avv = NTH ? ldv_nt<float, NT>(acc + off) : ldv<float, NT>(acc + off);
+          VecN<float, NT> avv = !live ? zerov<float, NT>() : NTH ? ldv_nt<float, NT>(acc + off) : ldv<float, NT>(acc + off);
           avv = add_terms<float, NT>(avv, m, al, pv, xs4[si], o);
           if (NTH) stv_nt<float, NT>(acc + off, avv);
           else stv<float, NT>(acc + off, avv);
@@ -428,14 +433,14 @@ __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hh
 
 namespace {
 
-template <bool SPLIT>
+template <bool SPLIT, bool PAD>
 const void *select_bf16_t(int nt_tiles, int u, int mode) {
 #define RFO_BF16_CASE(T, UU)                                                        \
   if (nt_tiles == T && u == UU)                                                     \
-    return mode == 1   ? (const void *)k_step9_bf16<T, UU, true, 1, SPLIT>          \
-           : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2, SPLIT>          \
-           : mode == 3 ? (const void *)k_step9_bf16<T, UU, true, 3, SPLIT>          \
-                       : (const void *)k_step9_bf16<T, UU, true, 0, SPLIT>;
+    return mode == 1   ? (const void *)k_step9_bf16<T, UU, true, 1, SPLIT, PAD>     \
+           : mode == 2 ? (const void *)k_step9_bf16<T, UU, true, 2, SPLIT, PAD>     \
+           : mode == 3 ? (const void *)k_step9_bf16<T, UU, true, 3, SPLIT, PAD>     \
+                       : (const void *)k_step9_bf16<T, UU, true, 0, SPLIT, PAD>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
   RFO_BF16_CASE(4, 4)
@@ -443,14 +448,15 @@ const void *select_bf16_t(int nt_tiles, int u, int mode) {
   return nullptr;
 }
 
-const void *select_bf16(int nt_tiles, int u, int mode, int split) {
-  return split ? select_bf16_t<true>(nt_tiles, u, mode) : select_bf16_t<false>(nt_tiles, u, mode);
+const void *select_bf16(int nt_tiles, int u, int mode, int split, bool pad) {
+  if (pad) return split ? select_bf16_t<true, true>(nt_tiles, u, mode) : select_bf16_t<false, true>(nt_tiles, u, mode);
+  return split ? select_bf16_t<true, false>(nt_tiles, u, mode) : select_bf16_t<false, false>(nt_tiles, u, mode);
 }
 
 }  // namespace
 
 int step_bf16_blocks_per_cu(int nt_tiles, int u, int split) {
-  const void *f = select_bf16(nt_tiles, u, 0, split);
+  const void *f = select_bf16(nt_tiles, u, 0, split, false);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -458,7 +464,7 @@ int step_bf16_blocks_per_cu(int nt_tiles, int u, int split) {
 }
 
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s) {
-  const void *f = select_bf16(nt_tiles, a.rpi, step_mode(a), a.hsplit);
+  const void *f = select_bf16(nt_tiles, a.rpi, step_mode(a), a.hsplit, a.s_live > 0 && a.s_live < a.sp);
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);

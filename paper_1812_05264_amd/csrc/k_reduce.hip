@@ -32,6 +32,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
   const int64_t I = sld(a.brow + nz);
   const int64_t J = sld(a.col + nz);
   const int sp = a.sp;
+  // zero-weight columns past s_live add nothing
+  const int c_end = a.s_live > 0 ? min(a.s_live, sp) : sp;
   double s[BD][BD];
 #pragma unroll
   for (int i = 0; i < BD; ++i)
@@ -42,7 +44,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(2))) void k
     const double coef = a.scale * ((a.j0 + t == 0) ? a.first : a.rest);
     const VT *X = static_cast<const VT *>(a.xbase) + (int64_t)t * a.xstride;
     const VT *Y = a.ybase ? static_cast<const VT *>(a.ybase) + (int64_t)t * a.ystride : nullptr;
-    for (int c = lane * PPL; c < sp; c += 64 * PPL) {
+    for (int c = lane * PPL; c < c_end; c += 64 * PPL) {
       double wc[PPL];
 #pragma unroll
       for (int q = 0; q < PPL; ++q) wc[q] = a.w[c + q] * coef;

@@ -72,12 +72,13 @@ __device__ __forceinline__ void zero_partials(double *prow, int n_pt, int wave, 
 // end load nothing and get zero weight (U = 7 fits a 7-point stencil row in one
 // chunk).  NT selects non-temporal hints for the streamed arrays.
 // ---------------------------------------------------------------------------
-template <typename VT, typename MT, int PPL, int U, int RPI, bool NT, int MODE>
+template <typename VT, typename MT, int PPL, int U, int RPI, bool NT, int MODE, bool PAD>
 __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
   const int wave = uniform(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int sp = a.sp;
   const int nw = sp >> 6;
+  const int s_live = a.s_live > 0 ? a.s_live : sp;
   const VT *__restrict__ x = static_cast<const VT *>(a.x);
   const VT *prev = static_cast<const VT *>(a.prev);
   VT *out = static_cast<VT *>(a.out);
@@ -128,6 +129,9 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
+    // PAD: a lane whose probes are all zero padding loads nothing (its inputs are
+    // zero); without padding columns the predicate is compiled out
+    const bool live = !PAD || c0 < s_live;
     const int64_t r0 = rg * a.rows_per_wg;
     const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
     for (int64_t I0 = r0 + wave * RPI; I0 < r1; I0 += kWaves * RPI) {
@@ -144,15 +148,16 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
 #pragma unroll
       for (int r = 0; r < RPI; ++r) {
         const int64_t off = Ir[r] * sp + c0;
-        if (has_prev) pv[r] = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        if (has_prev)
+          pv[r] = !live ? zerov<VT, PPL>() : NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
         if (SRC) {
 #pragma unroll
           for (int t = 0; t < 3; ++t)
-            if (t < nsrc) sv[t][r] = ldv_nt<VT, PPL>(srcp[t] + off);
+            if (t < nsrc) sv[t][r] = live ? ldv_nt<VT, PPL>(srcp[t] + off) : zerov<VT, PPL>();
         }
         if (need_r) {
           if (a.sgn) sw[r] = a.sgn[Ir[r] * nw + (c0 >> 6)];
-          else rv[r] = ldv<double, PPL>(a.rden + off);
+          else rv[r] = live ? ldv<double, PPL>(a.rden + off) : zerov<double, PPL>();
         }
       }
       VT s[RPI][PPL];
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
         for (int r = 0; r < RPI; ++r)
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            if (beg[r] + u < end[r]) xv[r][u] = ldv<VT, PPL>(x + J[r][u] * sp + c0);
+            if (beg[r] + u < end[r] && live) xv[r][u] = ldv<VT, PPL>(x + J[r][u] * sp + c0);
             else {
 #pragma unroll
               for (int q = 0; q < PPL; ++q) xv[r][u].v[q] = (VT)0;
@@ -207,7 +212,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
           }
 #pragma unroll
           for (int u = 0; u < U; ++u) {
-            if (nz0 + u < end[r]) xv[u] = ldv<VT, PPL>(x + J[u] * sp + c0);
+            if (nz0 + u < end[r] && live) xv[u] = ldv<VT, PPL>(x + J[u] * sp + c0);
             else {
 #pragma unroll
               for (int q = 0; q < PPL; ++q) xv[u].v[q] = (VT)0;
@@ -253,7 +258,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
         if (NT) stv_nt<VT, PPL>(out + off, o);
         else stv<VT, PPL>(out + off, o);
         if (m > 0) {
-          VecN<VT, PPL> av = NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
+          VecN<VT, PPL> av = !live ? zerov<VT, PPL>() : NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
           av = add_terms<VT, PPL>(av, m, al, pv[r], xs[r], o);
           if (NT) stv_nt<VT, PPL>(acc + off, av);
           else stv<VT, PPL>(acc + off, av);
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(kWG) void k_step1(StepArgs a) {
 // through the scalar cache instead serializes: sixteen waves per CU on
 // different block rows overflow it.)
 // ---------------------------------------------------------------------------
-template <typename VT, typename MT, int PPL, int U, bool NT, int MODE>
+template <typename VT, typename MT, int PPL, int U, bool NT, int MODE, bool PAD>
 __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   constexpr int BD = 9, BB = 81;
   constexpr int CH = U * BB;                       // H_hat values per chunk
@@ -283,6 +288,7 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
   const int lane = threadIdx.x & 63;
   const int sp = a.sp;
   const int nw = sp >> 6;
+  const int s_live = a.s_live > 0 ? a.s_live : sp;
   const VT *__restrict__ x = static_cast<const VT *>(a.x);
   const VT *prev = static_cast<const VT *>(a.prev);
   VT *out = static_cast<VT *>(a.out);
@@ -335,6 +341,9 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
       cur_pt = pt;
     }
     const int c0 = pt * (64 * PPL) + lane * PPL;
+    // PAD: a lane whose probes are all zero padding loads nothing (its inputs are
+    // zero); without padding columns the predicate is compiled out
+    const bool live = !PAD || c0 < s_live;
     const int64_t r0 = rg * a.rows_per_wg;
     const int64_t r1 = min(a.nb, r0 + (int64_t)a.rows_per_wg);
     // one scalar row of the output: shift, sources, moments, store, accumulator
@@ -342,14 +351,15 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
         const int64_t row = I * BD + i;
         const int64_t off = row * sp + c0;
         VecN<VT, PPL> pv, xs;
-        if (has_prev) pv = NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
+        if (has_prev)
+          pv = !live ? zerov<VT, PPL>() : NT ? ldv_nt<VT, PPL>(prev + off) : ldv<VT, PPL>(prev + off);
         VecN<VT, PPL> sv[3];
         if (SRC) {
 #pragma unroll
           for (int t = 0; t < 3; ++t)
-            if (t < nsrc) sv[t] = ldv_nt<VT, PPL>(srcp[t] + off);
+            if (t < nsrc) sv[t] = live ? ldv_nt<VT, PPL>(srcp[t] + off) : zerov<VT, PPL>();
         }
-        if (m >= 2 || DBL) xs = ldv<VT, PPL>(x + off);
+        if (m >= 2 || DBL) xs = live ? ldv<VT, PPL>(x + off) : zerov<VT, PPL>();
         double r[PPL];
         if (need_r) {
           if (a.sgn) {
@@ -357,7 +367,7 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
 #pragma unroll
             for (int q = 0; q < PPL; ++q) r[q] = ((w >> ((c0 + q) & 63)) & 1ull) ? 1.0 : -1.0;
           } else {
-            const VecN<double, PPL> rv = ldv<double, PPL>(a.rden + off);
+            const VecN<double, PPL> rv = live ? ldv<double, PPL>(a.rden + off) : zerov<double, PPL>();
 #pragma unroll
             for (int q = 0; q < PPL; ++q) r[q] = rv.v[q];
           }
@@ -386,7 +396,7 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
         if (NT) stv_nt<VT, PPL>(out + off, o);
         else stv<VT, PPL>(out + off, o);
         if (m > 0) {
-          VecN<VT, PPL> av = NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
+          VecN<VT, PPL> av = !live ? zerov<VT, PPL>() : NT ? ldv_nt<VT, PPL>(acc + off) : ldv<VT, PPL>(acc + off);
           av = add_terms<VT, PPL>(av, m, al, pv, xs, o);
           if (NT) stv_nt<VT, PPL>(acc + off, av);
           else stv<VT, PPL>(acc + off, av);
@@ -416,7 +426,8 @@ __global__ __launch_bounds__(kWG) void k_step9(StepArgs a) {
           // a chunk slot past the row's end gathers nothing (its FMAs are skipped)
           if (u == 0 || nz + u < end) {
 #pragma unroll
-            for (int j = 0; j < BD; ++j) xv[u][j] = ldv<VT, PPL>(x + (J[u] * BD + j) * sp + c0);
+            for (int j = 0; j < BD; ++j)
+              xv[u][j] = live ? ldv<VT, PPL>(x + (J[u] * BD + j) * sp + c0) : zerov<VT, PPL>();
           }
         }
       };
@@ -527,45 +538,49 @@ __global__ __launch_bounds__(kWG) void k_init(InitArgs a) {
 // ---------------------------------------------------------------------------
 namespace {
 
-template <typename VT, typename MT, int PPL, int MODE>
+template <typename VT, typename MT, int PPL, int MODE, bool PAD>
 const void *step_fn(int bd, int rpi) {
   // 1x1: rpi = rows per wave iteration with 8 neighbours per chunk, or 7: one
   // row per iteration with 7 neighbours per chunk; 9x9: rpi = blocks per chunk
   if (bd == 1) {
-    if (rpi == 7) return (const void *)k_step1<VT, MT, PPL, 7, 1, true, MODE>;
-    return rpi == 2 ? (const void *)k_step1<VT, MT, PPL, 8, 2, true, MODE>
-                    : (const void *)k_step1<VT, MT, PPL, 8, 1, true, MODE>;
+    if (rpi == 7) return (const void *)k_step1<VT, MT, PPL, 7, 1, true, MODE, PAD>;
+    return rpi == 2 ? (const void *)k_step1<VT, MT, PPL, 8, 2, true, MODE, PAD>
+                    : (const void *)k_step1<VT, MT, PPL, 8, 1, true, MODE, PAD>;
   }
-  return rpi == 2 ? (const void *)k_step9<VT, MT, PPL, 2, true, MODE>
-                  : (const void *)k_step9<VT, MT, PPL, 1, true, MODE>;
+  return rpi == 2 ? (const void *)k_step9<VT, MT, PPL, 2, true, MODE, PAD>
+                  : (const void *)k_step9<VT, MT, PPL, 1, true, MODE, PAD>;
 }
 
-template <typename VT, typename MT, int MODE>
+template <typename VT, typename MT, int MODE, bool PAD>
 const void *step_fn_t(int bd, int ppl, int rpi) {
   switch (ppl) {
-    case 1: return step_fn<VT, MT, 1, MODE>(bd, rpi);
-    case 2: return step_fn<VT, MT, 2, MODE>(bd, rpi);
-    case 4: return step_fn<VT, MT, 4, MODE>(bd, rpi);
+    case 1: return step_fn<VT, MT, 1, MODE, PAD>(bd, rpi);
+    case 2: return step_fn<VT, MT, 2, MODE, PAD>(bd, rpi);
+    case 4: return step_fn<VT, MT, 4, MODE, PAD>(bd, rpi);
     default: return nullptr;
   }
 }
 
-template <typename VT, typename MT>
+template <typename VT, typename MT, bool PAD>
 const void *step_fn_m(int bd, int ppl, int rpi, int mode) {
   switch (mode) {
-    case 0: return step_fn_t<VT, MT, 0>(bd, ppl, rpi);
-    case 1: return step_fn_t<VT, MT, 1>(bd, ppl, rpi);
-    case 2: return step_fn_t<VT, MT, 2>(bd, ppl, rpi);
-    case 3: return step_fn_t<VT, MT, 3>(bd, ppl, rpi);
+    case 0: return step_fn_t<VT, MT, 0, PAD>(bd, ppl, rpi);
+    case 1: return step_fn_t<VT, MT, 1, PAD>(bd, ppl, rpi);
+    case 2: return step_fn_t<VT, MT, 2, PAD>(bd, ppl, rpi);
+    case 3: return step_fn_t<VT, MT, 3, PAD>(bd, ppl, rpi);
     default: return nullptr;
   }
 }
 
-// mode: 0 plain, 1 density accumulator, 2 doubling moments, 3 vector sources
-const void *select_step(int bd, int precision, int ppl, int rpi, int mode) {
+// mode: 0 plain, 1 density accumulator, 2 doubling moments, 3 vector sources;
+// pad: some probe columns are zero padding (StepArgs::s_live)
+const void *select_step(int bd, int precision, int ppl, int rpi, int mode, bool pad) {
   if ((bd != 1 && bd != 9) || rpi < 1 || (rpi > 2 && !(bd == 1 && rpi == 7))) return nullptr;
-  return precision == 0 ? step_fn_m<double, double>(bd, ppl, rpi, mode)
-                        : step_fn_m<float, float>(bd, ppl, rpi, mode);
+  if (pad)
+    return precision == 0 ? step_fn_m<double, double, true>(bd, ppl, rpi, mode)
+                          : step_fn_m<float, float, true>(bd, ppl, rpi, mode);
+  return precision == 0 ? step_fn_m<double, double, false>(bd, ppl, rpi, mode)
+                        : step_fn_m<float, float, false>(bd, ppl, rpi, mode);
 }
 
 const void *select_init(int precision, int ppl) {
@@ -588,7 +603,7 @@ const void *select_init(int precision, int ppl) {
 }  // namespace
 
 int step_blocks_per_cu(int bd, int precision, int ppl, int rpi) {
-  const void *f = select_step(bd, precision, ppl, rpi, 0);
+  const void *f = select_step(bd, precision, ppl, rpi, 0, false);
   if (!f) return 0;
   int nblk = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nblk, f, kWG, 0) != hipSuccess) return 0;
@@ -596,7 +611,7 @@ int step_blocks_per_cu(int bd, int precision, int ppl, int rpi) {
 }
 
 hipError_t launch_step(int bd, int precision, int ppl, const StepArgs &a, hipStream_t s) {
-  const void *f = select_step(bd, precision, ppl, a.rpi, step_mode(a));
+  const void *f = select_step(bd, precision, ppl, a.rpi, step_mode(a), a.s_live > 0 && a.s_live < a.sp);
   if (!f || a.grid < 8 || (a.grid & 7)) return hipErrorInvalidValue;
   void *args[] = {const_cast<StepArgs *>(&a)};
   return hipLaunchKernel(f, dim3((unsigned)a.grid), dim3(kWG), args, 0, s);

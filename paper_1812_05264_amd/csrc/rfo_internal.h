@@ -58,6 +58,10 @@ struct StepArgs {
   int grid;                // workgroups (multiple of 8); part has [grid][sp]
   int reverse;             // sweep each XCD's range of units from its end
   int hsplit;              // BF16 steps: the pack holds hi and lo BF16 parts of H_hat
+  // probe columns at or past s_live are zero in every input vector (dense probes,
+  // whose padding columns are zero): a lane whose probes all lie there loads
+  // nothing and stores zeros.  0 = every column is live.
+  int s_live;
 };
 
 // Kernel variant of a step: 1 = density accumulator terms, 2 = doubling
@@ -162,6 +166,8 @@ struct SddmmArgs {
   int64_t nlist;
   int ppl;                 // probes per lane per load (1 or 2)
   int sym;                 // G[nz] (+)= sum_t coef_t sum_c w_c (X_I Y_J^T + Y_I X_J^T)
+  int s_live;              // columns at or past s_live have weight zero and are skipped
+                           // (0 = none)
 };
 hipError_t launch_sddmm(int precision, const SddmmArgs &a, hipStream_t s);
 
