@@ -120,7 +120,7 @@ def sc64_fp32(H, R, cfg, ref, dens64):
     b = step_bytes(H, s, 4, 4, density=True, p=p)
     gbs = b / (step_ms * 1e-3) / 1e9
     d64 = dens64.cpu().numpy()
-    out = {"kernel": "k_step1<float, float, 4, 7, 1, true, MODE>", "step_us": round(step_ms * 1e3, 2),
+    out = {"kernel": "k_step1<float, float, 4, 7, 1, true, MODE, false>", "step_us": round(step_ms * 1e3, 2),
            "bytes_per_hv_step": int(b), "GB_per_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
            "speedup_vs_fp64_step": None,
            "density_rel_diff": float(np.linalg.norm(g["density"] - d64) / np.linalg.norm(d64))}
@@ -632,8 +632,8 @@ def main():
     # the step kernel is launched as two variants: MODE 1 on the steps that
     # update the density accumulator, MODE 0 on the others (7 neighbours per
     # chunk: every row of the lattice has 7 entries)
-    kname = ("k_step1<double, double, 2, 7, 1, true, MODE>" if args.precision == "fp64"
-             else "k_step1<float, float, 4, 7, 1, true, MODE>")
+    kname = ("k_step1<double, double, 2, 7, 1, true, MODE, false>" if args.precision == "fp64"
+             else "k_step1<float, float, 4, 7, 1, true, MODE, false>")
     traffic = measured_traffic("sc64_" + args.precision)
     print(f"[bench] sc64 {args.precision}: {wall / args.steps * 1e3:.1f} ms per call, step kernel "
           f"{step_ms * 1e3:.1f} us ({n_steps} steps), {achieved:.0f} GB/s, N={last['N']:.6f}",
