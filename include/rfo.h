@@ -180,16 +180,40 @@ int rfo_traces_at(rfo_ctx *ctx, double T, double mu, double *NEF_out);
  * their vector sources; the result is the same gradient up to rounding.
  *   NEF_out   [3]  N, E, F of the forward pass (nullable)
  *   dFdH_out  [nnzb][bd][bd]  raw gradient G (nullable)
- * The gradient also stays on the device for rfo_hf_forces. */
+ * The gradient also stays on the device for rfo_hf_forces.
+ * With an overlap S (rfo_set_overlap) the derivative is that of F~ = sum_k beta_k
+ * r^T T_k(H_hat S^{-1}) r (paper: Eq. polynomial_response), taken by the direct
+ * recurrence (no moment doubling) with one conjugate-gradient solve per forward,
+ * replayed and reverse step: dFdH_out then holds the symmetric part of dF~/dH
+ * ((G_IJ + G_JI^T)/2, what symmetric variations of H see; with S != I the two halves
+ * differ), and dF~/dS, likewise symmetrized, stays on the device for
+ * rfo_get_dFdS and rfo_hf_forces_overlap.  Probe batches are not taken with an
+ * overlap: RFO_E_NOMEM when the vectors of all probes exceed the budget. */
 int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
                         double *NEF_out, double *dFdH_out);
+
+/* dF~/dS [nnzb][bd][bd] (symmetric part, host or device memory) of the last
+ * rfo_energy_and_dEdH call with an overlap (paper: Analytical free-energy
+ * derivatives, Eq. polynomial_response).  RFO_E_STATE without one. */
+int rfo_get_dFdS(rfo_ctx *ctx, double *dFdS_out);
+
+/* Forces from the last gradient with an overlap (paper: Observable response): for
+ * a two-centre model with dHdR, dSdR [nnzb][3][bd][bd] = d H_IJ / d R_I and
+ * d S_IJ / d R_I, force_a = -(sum <dF~/dH, dH/dR_a> + sum <dF~/dS, dS/dR_a>) over
+ * the stored blocks.  dSdR must be NULL exactly when the gradient has no overlap
+ * term (then this is rfo_hf_forces).  forces_out [n_block_rows][3].
+ * Errors: RFO_E_STATE before rfo_energy_and_dEdH or for dSdR without an overlap
+ * gradient; RFO_E_INVALID for a missing dSdR. */
+int rfo_hf_forces_overlap(rfo_ctx *ctx, const double *dHdR, const double *dSdR,
+                          double *forces_out);
 
 /* Hellmann-Feynman forces from the last gradient (paper: Observable
  * response with S = I): for a two-centre model with
  * dHdR [nnzb][3][bd][bd] = d H_IJ / d R_I for every stored block (host or
  * device memory), force_a = -(sum_J <G_aJ, D_aJ> - sum_I <G_Ia, D_Ia>).
  *   forces_out [n_block_rows][3].
- * Errors: RFO_E_STATE before rfo_energy_and_dEdH. */
+ * Errors: RFO_E_STATE before rfo_energy_and_dEdH, or when that gradient has an
+ * overlap term (use rfo_hf_forces_overlap). */
 int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out);
 
 /* Nonorthogonal basis (paper: Polynomial approximation with S, Eq. poly_PQ).
@@ -200,8 +224,8 @@ int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out);
  * by conjugate gradients to |residual| <= cg_tol |y| (cg_tol <= 0: 1e-13).  The
  * moments stay mu_k = r . y_k (N = tr[P S]); with density output the library
  * also forms the Q blocks (Q y = S^{-1} H S^{-1} sum_k alpha_k y_k).  Moment
- * doubling is not used (T_k(H_hat S^{-1}) is not symmetric) and
- * rfo_energy_and_dEdH returns RFO_E_UNSUPPORTED while S is set.
+ * doubling is not used (T_k(H_hat S^{-1}) is not symmetric); rfo_energy_and_dEdH
+ * then gives dF~/dH and dF~/dS (see there).
  * Requires FP64 precision and an interval passed to rfo_set_hamiltonian that
  * contains the spectrum of the pencil (H, S) (RFO_E_UNSUPPORTED / RFO_E_STATE
  * otherwise).  rfo_set_hamiltonian clears S.

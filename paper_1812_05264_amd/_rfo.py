@@ -54,6 +54,8 @@ def load():
     lib.rfo_energy_and_dEdH.argtypes = [vp, dbl, dbl, i64, vp, vp]
     lib.rfo_fermi_moments_noalloc.argtypes = [vp, dbl, dbl, i64, vp, vp]
     lib.rfo_hf_forces.argtypes = [vp, vp, vp]
+    lib.rfo_hf_forces_overlap.argtypes = [vp, vp, vp, vp]
+    lib.rfo_get_dFdS.argtypes = [vp, vp]
     lib.rfo_set_timing.argtypes = [vp, i32]
     lib.rfo_set_moment_doubling.argtypes = [vp, i32]
     lib.rfo_set_tuning.argtypes = [vp, i32, i64]
@@ -74,7 +76,7 @@ def load():
         "rfo_set_timing", "rfo_step_timing", "rfo_set_moment_doubling", "rfo_set_tuning",
         "rfo_traces_at", "rfo_set_overlap", "rfo_get_density_q", "rfo_density_forces",
         "rfo_cg_stats", "rfo_rational_fit", "rfo_rational_estimate", "rfo_rational_stats", "rfo_color_atoms",
-        "rfo_set_colored_probes"):
+        "rfo_set_colored_probes", "rfo_hf_forces_overlap", "rfo_get_dFdS"):
         getattr(lib, f).restype = i32
     _lib = lib
     return lib
@@ -266,6 +268,21 @@ class Engine:
             d = np.ascontiguousarray(dHdR, dtype=np.float64)
         out = np.empty((self.n_block_rows, 3))
         self._check(self._lib.rfo_hf_forces(self._ctx, _ptr(d), _ptr(out)))
+        return out
+
+    def hf_forces_overlap(self, dHdR, dSdR):
+        """-(sum <dF/dH, dH/dR_a> + sum <dF/dS, dS/dR_a>) from the last gradient with an
+        overlap, [n_block_rows, 3]."""
+        dH = _host(dHdR, np.float64)
+        dS = None if dSdR is None else _host(dSdR, np.float64)
+        out = np.empty((self.n_block_rows, 3))
+        self._check(self._lib.rfo_hf_forces_overlap(self._ctx, _ptr(dH), _ptr(dS), _ptr(out)))
+        return out
+
+    def dFdS(self):
+        """dF/dS blocks (symmetric part) of the last gradient with an overlap."""
+        out = np.empty((self.nnzb, self.block_dim, self.block_dim))
+        self._check(self._lib.rfo_get_dFdS(self._ctx, _ptr(out)))
         return out
 
     # -- instrumentation --------------------------------------------------------------

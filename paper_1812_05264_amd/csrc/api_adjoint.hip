@@ -350,6 +350,191 @@ int energy_grad_direct(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, size
   return RFO_OK;
 }
 
+// Free energy and gradient with an overlap S, by the direct recurrence (paper: Analytical
+// free-energy derivatives, Eq. polynomial_response; Polynomial approximation with S).
+// A = H_hat S^{-1}; the forward pass forms y_{k+1} = 2 H_hat t_k - y_{k-1}, t_k = S^{-1} y_k.
+// The reverse recurrence of the direct form runs with A^T = S^{-1} H_hat and is carried as
+// v_i = S z_i:
+//   v_{p-1} = beta_{p-1} S r,  v_i = 2 H_hat z_{i+1} - v_{i+2} + beta_i S r,  z_i = S^{-1} v_i,
+// so a reverse step is one step kernel and one conjugate-gradient solve, like a forward
+// step.  With c_0 = 1, c_j = 2, kappa = (e_max + e_min)/(e_max - e_min) and
+// A^T z_{j+1} = (z_j + z_{j+2} - beta_j r)/2 (the reverse recurrence itself; z_p = 0),
+//   dF/dH = 2/(e_max - e_min) sum_j c_j z_{j+1} t_j^T,
+//   dF/dS = -sum_j c_j (kappa z_{j+1} + A^T z_{j+1}) t_j^T,
+// both as their symmetric parts (A is not symmetric, and symmetric variations of H and S
+// see only that part), summed on the blocks on and above the diagonal and mirrored.
+// Memory: the sqrt(p) checkpoints of the direct form, and per segment t_j, z_j and the
+// dF/dS left factors.
+int energy_grad_overlap(rfo_ctx *ctx, const Plan &pl, int64_t p, size_t *n_events_out) {
+  const int kp = kernel_precision(ctx);
+  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
+  const int64_t P1 = p - 1;
+  int64_t m = 2;
+  while (m * m < P1) ++m;
+  const int64_t Q = P1 > 0 ? (P1 + m - 1) / m : 0;
+  // slots: 0, 1 y pair | 2 t of the forward pass | 3..5 CG work | 6 S r | 7, 8 v pair |
+  //        ts [m] | zs [m + 2] | xs [m] | checkpoints [2 (Q - 1)]
+  const int64_t o_sr = 6, o_v = 7, o_ts = 9, o_zs = o_ts + m, o_xs = o_zs + m + 2, o_ck = o_xs + m;
+  const int64_t n_ck = Q > 1 ? 2 * (Q - 1) : 0;
+  TRY(ensure(ctx, ctx->vec, (size_t)(o_ck + n_ck) * pl.slot_bytes));
+  TRY(ensure(ctx, ctx->GQ, gbytes));
+  TRY(ensure_cg(ctx));  // the solves' column partials and scalars
+  auto slot = [&](int64_t i) { return vec_at(ctx, pl, ctx->vec, i); };
+  DevBuf ckview;
+  ckview.p = slot(o_ck);
+  ckview.bytes = (size_t)n_ck * pl.slot_bytes;
+  Checkpoints ck;
+  ck.m = m;
+  ck.Q = Q;
+  ck.store = &ckview;
+  TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, n_events_out));
+  if (P1 == 0) {
+    HIPCHK(hipMemsetAsync(ctx->G.p, 0, gbytes, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->GQ.p, 0, gbytes, ctx->stream));
+    return RFO_OK;
+  }
+  std::vector<double> beta((size_t)p);
+  HIPCHK(hipMemcpyAsync(beta.data(), P<double>(ctx->coef) + 2 * p, p * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  const double *beta_d = P<double>(ctx->coef) + 2 * p;
+  const double kappa = (ctx->e_max + ctx->e_min) / (ctx->e_max - ctx->e_min);
+  const uint64_t *sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
+  const double *rden = ctx->signs ? nullptr : P<double>(ctx->rden);
+  auto dptr = [](char *c) { return reinterpret_cast<double *>(c); };
+
+  rfo::StepArgs sa;
+  fill_step(ctx, pl, sa);
+  rfo::InitArgs ia;
+  fill_init(ctx, pl, ia);
+  ia.scale = nullptr;
+  ia.acc = nullptr;
+  ia.part = nullptr;
+  // S r (slot 6), from r written into slot 2
+  ia.out = slot(2);
+  HIPCHK(launch_init_slot(ctx, pl, ia));
+  {
+    rfo::StepArgs ss = sa;
+    ss.hval = ctx->s64.p;
+    ss.x = slot(2);
+    ss.prev = nullptr;
+    ss.out = slot(o_sr);
+    ss.c1 = 1.0;
+    ss.c2 = 0.0;
+    HIPCHK(launch_any_step(ctx, pl, ss));
+  }
+  // reverse steps: the probe term beta_i S r comes from S r as a dense probe block (its
+  // padding columns are S times those of r: zero for dense probes, whose loads the
+  // padding variant skips, and computed in full for sign-bit probes)
+  rfo::StepArgs rs = sa;
+  rs.sgn = nullptr;
+  rs.rden = dptr(slot(o_sr));
+  auto ts = [&](int64_t t) { return slot(o_ts + t); };
+  auto zs = [&](int64_t t) { return slot(o_zs + t); };
+  auto xs = [&](int64_t t) { return slot(o_xs + t); };
+  auto cka = [&](int64_t q) { return slot(o_ck + 2 * (q - 1)); };
+  auto ckb = [&](int64_t q) { return slot(o_ck + 2 * (q - 1) + 1); };
+  const size_t vb = pl.slot_bytes;
+  char *vnear = slot(o_v), *vfar = slot(o_v + 1);  // v_{i+1}, v_{i+2} before step i
+  for (int64_t q = Q - 1; q >= 0; --q) {
+    const int64_t j0 = q * m, j1 = std::min(j0 + m, P1), len = j1 - j0;
+    // replay: ts[t] = t_{j0+t} = S^{-1} y_{j0+t}, y pair in slots 0 and 1
+    char *ycur = slot(0), *yprv = slot(1);
+    if (q == 0) {
+      ia.out = ycur;
+      ia.scale = nullptr;
+      HIPCHK(launch_init_slot(ctx, pl, ia));
+    } else {
+      HIPCHK(hipMemcpyAsync(ycur, ckb(q), vb, hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(yprv, cka(q), vb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    TRY(cg_solve(ctx, pl, ctx->vec, ycur, ts(0)));
+    for (int64_t t = 1; t < len; ++t) {
+      const bool first = j0 + t == 1;  // y_1 = H_hat t_0
+      sa.x = ts(t - 1);
+      sa.prev = first ? nullptr : yprv;
+      sa.out = yprv;
+      sa.c1 = first ? 1.0 : 2.0;
+      sa.c2 = first ? 0.0 : -1.0;
+      sa.beta = nullptr;
+      sa.acc = nullptr;
+      sa.part = nullptr;
+      HIPCHK(launch_any_step(ctx, pl, sa));
+      std::swap(ycur, yprv);
+      TRY(cg_solve(ctx, pl, ctx->vec, ycur, ts(t)));
+    }
+    // reverse: zs[t] = z_{j0+t}, t = 0 .. len + 1.  The top segment starts from
+    // z_{p-1} = beta_{p-1} r and v_{p-1} = beta_{p-1} S r (z_p = 0 is not stored); the
+    // others find z_{j1}, z_{j1+1} in zs[len], zs[len+1] and v_{j1}, v_{j1+1} in the v pair
+    if (q == Q - 1) {
+      ia.out = zs(len);
+      ia.scale = beta_d + (p - 1);
+      HIPCHK(launch_init_slot(ctx, pl, ia));
+      ia.scale = nullptr;
+      HIPCHK(rfo::launch_combine(dptr(vnear), beta[(size_t)(p - 1)], dptr(slot(o_sr)), 0.0, nullptr, 0.0,
+                                 nullptr, 0.0, nullptr, nullptr, ctx->n, ctx->sp, ctx->stream));
+    }
+    for (int64_t i = j1 - 1; i >= j0; --i) {
+      const bool top = i == p - 2;  // v_{i+2} = v_p = 0
+      rs.x = zs(i + 1 - j0);
+      rs.prev = top ? nullptr : vfar;
+      rs.out = vfar;
+      rs.c1 = 2.0;
+      rs.c2 = top ? 0.0 : -1.0;
+      rs.beta = beta_d + i;
+      rs.acc = nullptr;
+      rs.part = nullptr;
+      HIPCHK(launch_any_step(ctx, pl, rs));
+      std::swap(vnear, vfar);  // vnear = v_i, vfar = v_{i+1}
+      TRY(cg_solve(ctx, pl, ctx->vec, vnear, zs(i - j0)));
+    }
+    // dF/dS left factors xs[t] = kappa z_{j+1} + (z_j + z_{j+2} - beta_j r)/2, j = j0 + t
+    for (int64_t t = 0; t < len; ++t) {
+      const int64_t j = j0 + t;
+      const bool zp = j + 2 == p;  // z_p = 0
+      HIPCHK(rfo::launch_combine(dptr(xs(t)), kappa, dptr(zs(t + 1)), 0.5, dptr(zs(t)), zp ? 0.0 : 0.5,
+                                 zp ? nullptr : dptr(zs(t + 2)), -0.5 * beta[(size_t)j], sgn, rden, ctx->n,
+                                 ctx->sp, ctx->stream));
+    }
+    // G (+)= the symmetric parts: sum_t coef_t (X_I t_J^T + t_I X_J^T) / 2 over the segment
+    rfo::SddmmArgs a;
+    memset(&a, 0, sizeof(a));
+    a.brow = P<int64_t>(ctx->brow);
+    a.col = P<int32_t>(ctx->col);
+    a.nnzb = ctx->nnzb;
+    a.bd = ctx->bd;
+    a.sp = ctx->sp;
+    a.xstride = (int64_t)(pl.slot_bytes / pl.vt_bytes);
+    a.ybase = ts(0);
+    a.ystride = a.xstride;
+    a.w = P<double>(ctx->w);
+    a.count = (int)len;
+    a.j0 = j0;
+    a.first = 1.0;
+    a.rest = 2.0;
+    a.accumulate = q == Q - 1 ? 0 : 1;
+    a.nzlist = P<int64_t>(ctx->nz_up);
+    a.nlist = ctx->n_up;
+    a.ppl = sddmm_ppl(ctx);
+    a.sym = 1;
+    a.s_live = (int)ctx->s;
+    a.xbase = zs(1);
+    a.scale = 1.0 / (ctx->e_max - ctx->e_min);
+    a.G = P<double>(ctx->G);
+    HIPCHK(launch_sddmm_segment(ctx, kp, a, pl.slot_bytes, ctx->stream));
+    a.xbase = xs(0);
+    a.scale = -0.5;
+    a.G = P<double>(ctx->GQ);
+    HIPCHK(launch_sddmm_segment(ctx, kp, a, pl.slot_bytes, ctx->stream));
+    if (q > 0) {
+      // the segment below starts from z_{j0}, z_{j0+1} (its zs[m], zs[m+1]) and v_{j0}, v_{j0+1}
+      HIPCHK(hipMemcpyAsync(zs(m), zs(0), vb, hipMemcpyDeviceToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(zs(m + 1), zs(1), vb, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+  }
+  return RFO_OK;
+}
+
 // Bytes of the adjoint's vector slots for the current probes (doubled or direct
 // form; see the two functions above).
 size_t adjoint_slot_bytes(const rfo_ctx *ctx, const Plan &pl, int64_t p, bool dbl) {
@@ -358,6 +543,7 @@ size_t adjoint_slot_bytes(const rfo_ctx *ctx, const Plan &pl, int64_t p, bool db
   while (m * m < K) ++m;
   const int64_t Q = K > 0 ? (K + m - 1) / m : 0;
   const int64_t n_ck = Q > 1 ? 2 * (Q - 1) : 0;
+  if (ctx->has_s) return (size_t)(9 + 3 * m + 2 + n_ck) * pl.slot_bytes;  // energy_grad_overlap
   const int n_sets = dbl && Q > 1 && tuned(ctx, RFO_TUNE_OVERLAP, 0) != 0 ? 2 : 1;
   const int64_t slots = dbl ? n_sets * 2 * (m + 2) + n_ck : m + (m + 2) + n_ck;
   return (size_t)std::max<int64_t>(slots, 2) * pl.slot_bytes;
@@ -385,11 +571,8 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   Plan pl;
   TRY(prepare_call(ctx, T, mu, n_terms, pl));
   const int64_t p = n_terms;
-  if (ctx->has_s)
-    return fail(ctx, RFO_E_UNSUPPORTED,
-                "the free-energy gradient with an overlap is not implemented; use the density "
-                "blocks and rfo_density_forces");
-  const bool dbl = ctx->doubling && p >= 2;
+  // with an overlap the direct recurrence (moment doubling needs a symmetric H_hat)
+  const bool dbl = ctx->doubling && p >= 2 && !ctx->has_s;
   const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
   TRY(ensure(ctx, ctx->G, gbytes));
   ctx->has_grad = false;
@@ -411,12 +594,16 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   if ((size_t)width * per_probe > budget)
     return fail(ctx, RFO_E_NOMEM, "the adjoint needs %zu bytes of vectors for one batch of 64 probes; "
                 "the budget is %zu", (size_t)64 * per_probe, budget);
+  if (ctx->has_s && width < ctx->sp)
+    return fail(ctx, RFO_E_NOMEM, "the gradient with an overlap needs %zu bytes of vectors; the budget "
+                "is %zu (probe batches are not taken with an overlap)", (size_t)ctx->sp * per_probe, budget);
   double *obs = P<double>(ctx->small);
   if (width >= ctx->sp) {
     TRY(ensure(ctx, ctx->vec, adjoint_slot_bytes(ctx, pl, p, dbl)));
     size_t n_events = 0;
-    TRY(dbl ? energy_grad_doubling(ctx, pl, p, false, &n_events)
-            : energy_grad_direct(ctx, pl, p, false, &n_events));
+    TRY(ctx->has_s ? energy_grad_overlap(ctx, pl, p, &n_events)
+        : dbl      ? energy_grad_doubling(ctx, pl, p, false, &n_events)
+                   : energy_grad_direct(ctx, pl, p, false, &n_events));
     HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
                               ctx->sp, obs, ctx->stream));
     TRY(check_flags_and_finish(ctx, n_events));
@@ -504,10 +691,15 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   }
   HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
                             P<double>(ctx->G), ctx->stream));
+  if (ctx->has_s)
+    HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
+                              P<double>(ctx->GQ), ctx->stream));
   TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
   TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   ctx->has_grad = true;
+  ctx->grad_s = ctx->has_s;
+  ctx->has_q = false;  // with an overlap GQ now holds dF/dS
   ctx->has_dens = false;
   ctx->mom_p = p;
   return RFO_OK;
@@ -517,16 +709,46 @@ int rfo_hf_forces(rfo_ctx *ctx, const double *dHdR, double *forces_out) {
   if (!ctx) return RFO_E_INVALID;
   ctx->err.clear();
   if (!ctx->has_grad) return fail(ctx, RFO_E_STATE, "no gradient: call rfo_energy_and_dEdH first");
+  if (ctx->grad_s)
+    return fail(ctx, RFO_E_STATE, "the gradient has an overlap term: use rfo_hf_forces_overlap");
+  return rfo_hf_forces_overlap(ctx, dHdR, nullptr, forces_out);
+}
+
+int rfo_hf_forces_overlap(rfo_ctx *ctx, const double *dHdR, const double *dSdR, double *forces_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_grad) return fail(ctx, RFO_E_STATE, "no gradient: call rfo_energy_and_dEdH first");
   if (!dHdR || !forces_out) return fail(ctx, RFO_E_INVALID, "NULL argument");
+  if (ctx->grad_s && !dSdR) return fail(ctx, RFO_E_INVALID, "the gradient has an overlap term: dSdR is NULL");
+  if (!ctx->grad_s && dSdR) return fail(ctx, RFO_E_STATE, "the last gradient has no overlap term");
   HIPCHK(hipSetDevice(ctx->device));
   const size_t dbytes = (size_t)ctx->nnzb * 3 * ctx->bd * ctx->bd * sizeof(double);
   TRY(ensure(ctx, ctx->dHdR, dbytes));
   TRY(ensure(ctx, ctx->forces, (size_t)ctx->nb * 3 * sizeof(double)));
   HIPCHK(hipMemcpyAsync(ctx->dHdR.p, dHdR, dbytes, hipMemcpyDefault, ctx->stream));
+  // force_a = -(sum <dF/dH, dH/dR_a> + sum <dF/dS, dS/dR_a>) over the stored blocks
   HIPCHK(rfo::launch_forces(P<int64_t>(ctx->row_ptr), P<int64_t>(ctx->tpos), P<double>(ctx->G),
                             P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces), 1.0, 0,
                             ctx->stream));
+  if (dSdR) {
+    HIPCHK(hipMemcpyAsync(ctx->dHdR.p, dSdR, dbytes, hipMemcpyDefault, ctx->stream));
+    HIPCHK(rfo::launch_forces(P<int64_t>(ctx->row_ptr), P<int64_t>(ctx->tpos), P<double>(ctx->GQ),
+                              P<double>(ctx->dHdR), ctx->nb, ctx->bd, P<double>(ctx->forces), 1.0, 1,
+                              ctx->stream));
+  }
   TRY(copy_out(ctx, forces_out, ctx->forces.p, (size_t)ctx->nb * 3 * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  return RFO_OK;
+}
+
+int rfo_get_dFdS(rfo_ctx *ctx, double *dFdS_out) {
+  if (!ctx) return RFO_E_INVALID;
+  ctx->err.clear();
+  if (!ctx->has_grad || !ctx->grad_s)
+    return fail(ctx, RFO_E_STATE, "no overlap gradient: call rfo_energy_and_dEdH with an overlap first");
+  if (!dFdS_out) return fail(ctx, RFO_E_INVALID, "dFdS_out is NULL");
+  HIPCHK(hipSetDevice(ctx->device));
+  TRY(copy_out(ctx, dFdS_out, ctx->GQ.p, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->stream));
   return RFO_OK;
 }

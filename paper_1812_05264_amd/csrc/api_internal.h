@@ -57,6 +57,7 @@ struct rfo_ctx {
   // work buffers
   DevBuf vec, acc, ring, moments, coef, samples, costab, small, flags, G, dHdR, forces;
   bool has_grad = false;
+  bool grad_s = false;  // the gradient of the last rfo_energy_and_dEdH has dF/dS (in GQ)
 
   bool doubling = true;  // moment-only calls via T_2j, T_2j-1 identities
   // launch geometry and schedule (rfo_set_tuning); -1 = the measured default
@@ -422,6 +423,10 @@ inline int ensure_cg(rfo_ctx *ctx) {
 inline int cg_solve(rfo_ctx *ctx, const Plan &pl, DevBuf &bufs, const void *y, void *t) {
   const int64_t n = ctx->n;
   const int sp = ctx->sp;
+  // the kernels below write these buffers: never launch them unallocated or too small
+  if (!ctx->cg_res_h || ctx->cg_part.bytes < (size_t)rfo::cg_nparts(n) * sp * sizeof(double) ||
+      ctx->cg_sc.bytes < ((size_t)6 * sp + 1) * sizeof(double) || bufs.bytes < 6 * pl.slot_bytes)
+    return fail(ctx, RFO_E_STATE, "internal: conjugate-gradient buffers not allocated");
   double *r = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 3));
   double *pv = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 4));
   double *q = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 5));

@@ -218,4 +218,35 @@ hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, in
   return hipGetLastError();
 }
 
+// out = ca A + cb B + cc C + cr r (a null operand or a zero weight adds nothing; r is the
+// probe block, sign bits or dense)
+__global__ __launch_bounds__(kWG) void k_combine(double *__restrict__ out, double ca, const double *A,
+                                                 double cb, const double *B, double cc, const double *C,
+                                                 double cr, const uint64_t *__restrict__ sgn,
+                                                 const double *__restrict__ rden, int64_t n, int sp) {
+  const int64_t total = n * sp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    if (A && ca != 0.0) v = fma(ca, A[e], v);
+    if (B && cb != 0.0) v = fma(cb, B[e], v);
+    if (C && cc != 0.0) v = fma(cc, C[e], v);
+    if (cr != 0.0) {
+      const int64_t row = e / sp;
+      v = fma(cr, probe_value(sgn, rden, row, sp, (int)(e - row * sp)), v);
+    }
+    out[e] = v;
+  }
+}
+
+hipError_t launch_combine(double *out, double ca, const double *A, double cb, const double *B, double cc,
+                          const double *C, double cr, const uint64_t *sgn, const double *rden, int64_t n,
+                          int sp, hipStream_t s) {
+  int64_t blocks = (n * sp + kWG - 1) / kWG;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_combine, dim3((unsigned)blocks), dim3(kWG), 0, s, out, ca, A, cb, B, cc, C, cr, sgn,
+                     rden, n, sp);
+  return hipGetLastError();
+}
+
 }  // namespace rfo

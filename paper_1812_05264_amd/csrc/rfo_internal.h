@@ -231,6 +231,11 @@ hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, in
 // beta] (sp each).
 // ---------------------------------------------------------------------------
 hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out, hipStream_t s);
+// out = ca A + cb B + cc C + cr r over n rows of sp FP64 columns (null operands add nothing;
+// r from sgn or rden as in the step kernels)
+hipError_t launch_combine(double *out, double ca, const double *A, double cb, const double *B, double cc,
+                          const double *C, double cr, const uint64_t *sgn, const double *rden, int64_t n,
+                          int sp, hipStream_t s);
 
 // out = (H_hat - z) x, with the column partials of |out_c|^2 when part != nullptr
 // ([grid][sp]); same unit decomposition as the Chebyshev step (the value and

@@ -144,7 +144,80 @@ def test_overlap_errors():
         eng.set_overlap(bad)
     eng.set_overlap(S)
     eng.set_probes(rademacher(H.n, 8, config_id=66))
-    with pytest.raises(pkg.RfoError):                  # no gradient with an overlap
-        eng.energy_and_dEdH(0.3, 0.0, 20)
+    with pytest.raises(pkg.RfoError):                  # no overlap gradient yet
+        eng.dFdS()
+    eng.energy_and_dEdH(0.3, 0.0, 20)
+    D = np.zeros((H.nnzb, 3, 9, 9))
+    with pytest.raises(pkg.RfoError):                  # the gradient has an overlap term
+        eng.hf_forces(D)
+    with pytest.raises(pkg.RfoError):                  # ... so dSdR is required
+        eng.hf_forces_overlap(D, None)
     with pytest.raises(pkg.RfoError):                  # no density yet
-        eng.density_forces(np.zeros((H.nnzb, 3, 9, 9)))
+        eng.density_forces(D)
+
+
+@pytest.mark.parametrize("case", ["cu43_s72", "cu19_dense", "sc6_s100", "cu13_p2"])
+def test_overlap_gradient_matches_oracle(case):
+    """dF~/dH and dF~/dS with an overlap (Analytical free-energy derivatives, Eq.
+    polynomial_response) against the oracle's form of the same derivative (left vectors
+    T_j(S^{-1} H_hat) r, right vectors S^{-1} times U-polynomial sums), both as symmetric parts;
+    several checkpoint segments (cu43: 79 gradient terms in segments of 9), dense probes with
+    unequal weights, 1x1 blocks, and the shortest series with a gradient term."""
+    banner(f"overlap gradient parity {case}")
+    eng = engine_or_skip()
+    w = None
+    if case == "cu43_s72":
+        _, H, S = cu_system(43, 67)
+        R = rademacher(H.n, 72, config_id=68)
+        T, mu, p = 0.3, 0.2, 80
+    elif case == "cu19_dense":
+        _, H, S = cu_system(19, 69)
+        R = rademacher(H.n, 37, config_id=70) * (1.0 + 0.25 * np.cos(np.arange(H.n)))[:, None]
+        w = np.linspace(0.5, 1.5, 37) / 37
+        T, mu, p = 0.3, 0.2, 31
+    elif case == "sc6_s100":
+        H, S = sc_system(6, 71)
+        R = rademacher(H.n, 100, config_id=72)
+        T, mu, p = 0.2, 0.1, 60
+    else:
+        _, H, S = cu_system(13, 73)
+        R = rademacher(H.n, 16, config_id=74)
+        T, mu, p = 0.3, 0.2, 2
+    load(eng, H, S)
+    eng.set_probes(R, w)
+    g = eng.energy_and_dEdH(T, mu, p)
+    GS = eng.dFdS()
+    F, oH, oS = ov.free_energy_gradient(H, S, R, T, mu, p, weights=w)
+    assert abs(g["F"] - F) <= TOL * max(1.0, abs(F))
+    eH = check_blocks(g["dFdH"], oH, what="dF/dH")
+    eS = check_blocks(GS, oS, what="dF/dS")
+    print(f"{case}: dF/dH {eH:.2e}, dF/dS {eS:.2e} per block")
+    again = eng.energy_and_dEdH(T, mu, p)
+    assert np.array_equal(again["dFdH"], g["dFdH"]) and np.array_equal(eng.dFdS(), GS)
+
+
+def test_overlap_gradient_forces_match_finite_differences():
+    """Forces -(sum <dF~/dH, dH/dR> + sum <dF~/dS, dS/dR>) from the GPU gradient against central
+    differences of the oracle's F~ in the atom positions (same probes, fixed interval)."""
+    banner("overlap gradient forces vs finite differences")
+    eng = engine_or_skip()
+    cl, H, S = cu_system(13, 75)
+    R = rademacher(H.n, 16, config_id=76)
+    T, mu, p, h = 0.4, 0.3, 60, 1e-4
+    load(eng, H, S)
+    eng.set_probes(R)
+    eng.energy_and_dEdH(T, mu, p)
+    f = eng.hf_forces_overlap(cl.dH_dR(), dS_dR(cl))
+
+    def F_at(pos):
+        return ov.estimate(H.with_values(cl.values_at(pos)), overlap_values(cl, pos), R, T, mu, p)["F"]
+
+    worst = 0.0
+    for a in range(cl.n_atoms):
+        for d in range(3):
+            dp = np.zeros_like(cl.positions)
+            dp[a, d] = h
+            fd = (F_at(cl.positions + dp) - F_at(cl.positions - dp)) / (2 * h)
+            worst = max(worst, abs(fd + f[a, d]))
+    print(f"max |FD + gradient force| {worst:.2e} eV/A (largest force {np.max(np.abs(f)):.2e})")
+    assert worst < 1e-6
