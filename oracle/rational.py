@@ -19,7 +19,8 @@ Analytical free-energy derivatives:
   * the rational free-energy primitive F(y) = g0 y.y + g1 y.H y
         + 2 Re sum_k tau_k y^T G(z_k) y and its derivative (Eq.
     rational_derivative with dS = 0): dF(y)/dH_ab = g1 y_a y_b
-        - 2 Re sum_k tau_k g_{k,a} g_{k,b}   (G(z)^T = G(z) for symmetric H).
+        - 2 Re sum_k tau_k g_{k,a} g_{k,b}   (G(z)^T = G(z) for symmetric H);
+    with an overlap, the derivative with respect to H and S (gradient_overlap).
 
 The paper's fastest fit is a numerical one whose poles are not printed.  The
 fit here is the analytical kind the paper also names, valid on a finite
@@ -190,6 +191,51 @@ def estimate(bsr, R, fit, weights=None, density=False, gradient=False):
             G = G - 2.0 * np.real(tk * masked_outer_complex(bsr, gk, gk, w))
         out["dFdH"] = G
     return out
+
+
+def gradient_overlap(bsr, S_values, R, fit, weights=None):
+    """(F, G_H, G_S): the probe estimate of F with an overlap (as estimate_overlap) and its
+    derivatives with respect to the blocks of H and S, from the rational free-energy
+    derivative (Eq. rational_derivative) with the linear part of g added:
+
+      F_c = g0 r.r + g1 r^T H S^{-1} r + 2 Re sum_k tau_k r^T S G_k r,  G_k = (H - z_k S)^{-1},
+      dF_c = g1 [r^T dH S^{-1} r - (S^{-1} H r)^T dS S^{-1} r]
+             + 2 Re sum_k tau_k [r^T dS g_k + h_k^T (z_k dS - dH) g_k],
+
+    with g_k = G_k r and h_k = G_k S r (G_k^T = G_k for symmetric H and S).  On every stored
+    block (I, J):
+      G_H[I, J] = sum_c w_c [g1 r[I] (S^{-1} r)[J]^T - 2 Re sum_k tau_k h_k[I] g_k[J]^T],
+      G_S[I, J] = sum_c w_c [-g1 (S^{-1} H r)[I] (S^{-1} r)[J]^T
+                             + 2 Re sum_k tau_k (r[I] g_k[J]^T + z_k h_k[I] g_k[J]^T)],
+    each returned as its symmetric part (G[I, J] + G[J, I]^T)/2 (with S = I, G_H is already
+    symmetric and equals estimate's dFdH).  Solves by sparse LU."""
+    R = np.asarray(R, dtype=np.float64)
+    s = R.shape[1]
+    w = est.default_weights(s) if weights is None else np.asarray(weights, dtype=np.float64)
+    H = bsr.to_scipy().tocsr().astype(np.float64)
+    S = bsr.with_values(S_values).to_scipy().tocsr().astype(np.float64)
+    z, wg = fit["poles"], fit["res_g"]
+    gs = shifted_solves(H, R, z, S)
+    SR = S @ R
+    hs = shifted_solves(H, SR, z, S)
+    lu = spla.splu(sp.csc_matrix(S))
+    SiR = lu.solve(R)
+    SiHR = lu.solve(H @ R)
+    F = float(w @ (fit["g0"] * np.einsum("ic,ic->c", R, R)
+                   + fit["g1"] * np.einsum("ic,ic->c", H @ R, SiR)
+                   + 2.0 * np.real(sum(tk * np.einsum("ic,ic->c", SR, gk) for tk, gk in zip(wg, gs)))))
+    GH = fit["g1"] * est.masked_outer(bsr, R, SiR, w)
+    GS = -fit["g1"] * est.masked_outer(bsr, SiHR, SiR, w)
+    for tk, zk, gk, hk in zip(wg, z, gs, hs):
+        GH = GH - 2.0 * np.real(tk * masked_outer_complex(bsr, hk, gk, w))
+        GS = GS + 2.0 * np.real(tk * (masked_outer_complex(bsr, R.astype(np.complex128), gk, w)
+                                      + zk * masked_outer_complex(bsr, hk, gk, w)))
+    rows = bsr.block_rows()
+    cols = bsr.col_idx.astype(np.int64)
+    pos = {(int(i), int(j)): q for q, (i, j) in enumerate(zip(rows, cols))}
+    tp = np.array([pos[(int(j), int(i))] for i, j in zip(rows, cols)], dtype=np.int64)
+    sym = lambda G: 0.5 * (G + np.transpose(G[tp], (0, 2, 1)))   # noqa: E731
+    return F, sym(GH), sym(GS)
 
 
 def exact(H_dense, fit, S_dense=None):

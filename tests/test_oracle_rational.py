@@ -175,3 +175,72 @@ def test_overlap_identity_probes_give_generalized_traces_and_P_Q():
     e = ov.exact(H.to_dense(), Sd, T, mu, H.e_min, H.e_max)
     for k in ("N", "E", "F"):
         assert abs(o[k] - e[k]) < 1e-8 * max(1.0, abs(e[k])), k
+
+
+# --- the rational free-energy derivative with an overlap (Eq. rational_derivative, dS != 0) ---
+
+def _sym_direction(H, rng):
+    tpos = {(int(i), int(j)): nz for nz, (i, j) in enumerate(zip(H.block_rows(), H.col_idx))}
+    d = rng.standard_normal(H.values.shape)
+    sym = np.empty_like(d)
+    for (i, j), nz in tpos.items():
+        sym[nz] = 0.5 * (d[nz] + d[tpos[(j, i)]].T)
+    return sym
+
+
+def test_overlap_gradient_matches_finite_differences():
+    """<dF/dH, dH> + <dF/dS, dS> against central differences of the overlap estimate along
+    symmetric directions on the block pattern (H and S separately)."""
+    H, S = overlap_system(13, 66)
+    T, mu = 0.3, 0.2
+    fit = ra.contour_fit(24, T, mu, H.e_min, H.e_max)
+    R = rademacher(H.n, 4, config_id=67)
+    F, GH, GS = ra.gradient_overlap(H, S, R, fit)
+    assert abs(F - ra.estimate_overlap(H, S, R, fit)["F"]) < 1e-12 * abs(F)
+    rng = np.random.default_rng(68)
+    eps = 1e-5
+    for which in ("H", "S"):
+        for _ in range(2):
+            d = _sym_direction(H, rng)
+            if which == "H":
+                Fp = ra.estimate_overlap(H.with_values(H.values + eps * d), S, R, fit)["F"]
+                Fm = ra.estimate_overlap(H.with_values(H.values - eps * d), S, R, fit)["F"]
+                an = float(np.sum(GH * d))
+            else:
+                Fp = ra.estimate_overlap(H, S + eps * d, R, fit)["F"]
+                Fm = ra.estimate_overlap(H, S - eps * d, R, fit)["F"]
+                an = float(np.sum(GS * d))
+            fd = (Fp - Fm) / (2 * eps)
+            assert abs(fd - an) < 1e-7 * max(1.0, abs(an)), (which, fd, an)
+
+
+def test_overlap_gradient_identity_probes_closed_form():
+    """R = I, weights 1: F = sum_i g_rat(eps_i) over the generalized eigenvalues, so
+    dF/dH = V diag(g_rat'(eps)) V^T and dF/dS = -V diag(g_rat'(eps) eps) V^T (first-order
+    perturbation of H v = eps S v, V^T S V = I), g_rat' = g1 - 2 Re sum_k tau_k/(x - z_k)^2."""
+    import scipy.linalg as sl
+    H, S = overlap_system(13, 69)
+    T, mu = 0.3, 0.2
+    fit = ra.contour_fit(20, T, mu, H.e_min, H.e_max)
+    F, GH, GS = ra.gradient_overlap(H, S, identity_probes(H.n), fit, weights=np.ones(H.n))
+    eps, V = sl.eigh(H.to_dense(), H.with_values(S).to_dense())
+    assert abs(F - float(np.sum(ra.evaluate(fit, eps, "g")))) < 1e-10 * max(1.0, abs(F))
+    gp = fit["g1"] - 2.0 * np.real((fit["res_g"][None, :] / (eps[:, None] - fit["poles"][None, :]) ** 2).sum(axis=1))
+    dH = (V * gp) @ V.T
+    dS = -(V * (gp * eps)) @ V.T
+    rows, cols = H.block_rows(), H.col_idx.astype(np.int64)
+    blk = lambda M: np.stack([M[9 * i:9 * i + 9, 9 * j:9 * j + 9] for i, j in zip(rows, cols)])  # noqa: E731
+    assert np.max(np.abs(GH - blk(dH))) < 1e-10 * np.max(np.abs(blk(dH)))
+    assert np.max(np.abs(GS - blk(dS))) < 1e-10 * np.max(np.abs(blk(dS)))
+
+
+def test_overlap_gradient_with_identity_overlap_is_the_orthogonal_one():
+    H = cu_cluster(19, config_id=70).bsr()
+    I = np.zeros_like(H.values)
+    I[H.block_rows() == H.col_idx] = np.eye(9)
+    R = rademacher(H.n, 5, config_id=70)
+    fit = ra.contour_fit(16, 0.3, 0.1, H.e_min, H.e_max)
+    F, GH, _ = ra.gradient_overlap(H, I, R, fit)
+    e = ra.estimate(H, R, fit, gradient=True)
+    assert abs(F - e["F"]) < 1e-12 * abs(e["F"])
+    assert np.max(np.abs(GH - e["dFdH"])) < 1e-12 * np.max(np.abs(e["dFdH"]))
