@@ -315,11 +315,18 @@ int rfo_rational_fit(int n_nodes, double T, double mu, double e_min, double e_ma
  *   N = sum_c w_c (S r_c).(P r_c),  E = sum_c w_c (H r_c).(P r_c),
  *   F = sum_c w_c [g0 r_c.r_c + g1 (H r_c).(S^{-1} r_c) + 2 Re sum_k tau_k (S r_c).g_k],
  * with S^{-1} by conjugate gradients (the overlap's cg_tol); the density call
- * then also forms the Q blocks (rfo_get_density_q), and dFdH_out must be NULL.
- * After the call rfo_hf_forces uses this gradient (if requested), and
- * rfo_density_forces this density (if requested without the gradient).
- * Requires FP64 precision (RFO_E_UNSUPPORTED otherwise, and for the gradient
- * with an overlap).
+ * then also forms the Q blocks (rfo_get_density_q).  The gradient with an overlap
+ * (Eq. rational_derivative with dS, and the linear part of g) takes a second solve
+ * per pole, h_k = (H - z_k S)^{-1} S r_c: dFdH_out holds the symmetric part of
+ *   dF/dH = sum_c w_c [g1 r_c (S^{-1} r_c)^T - 2 Re sum_k tau_k h_k g_k^T]
+ * and dF/dS, likewise symmetrized,
+ *   dF/dS = sum_c w_c [-g1 (S^{-1} H r_c)(S^{-1} r_c)^T + 2 Re sum_k tau_k (r_c g_k^T + z_k h_k g_k^T)],
+ * stays on the device for rfo_get_dFdS and rfo_hf_forces_overlap; density and
+ * gradient are then requested in separate calls (RFO_E_UNSUPPORTED otherwise).
+ * After the call rfo_hf_forces (S = I) or rfo_hf_forces_overlap uses this
+ * gradient (if requested), and rfo_density_forces this density (if requested
+ * without the gradient).
+ * Requires FP64 precision (RFO_E_UNSUPPORTED otherwise).
  * Errors: RFO_E_STATE before H and probes; RFO_E_INVALID for bad arguments;
  * RFO_E_NUMERIC if CGLS breaks down or does not converge within max_iter. */
 int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double *poles,

@@ -311,7 +311,8 @@ class Engine:
         """Rational estimate with the fit dict of rational_fit (or any poles/residues of
         the same form).  Returns dict(N, E, F, density, dFdH, iterations).  With an
         overlap set the shifted systems are (H - z S) g = r, density_q() then holds the
-        Q blocks of the call, and the gradient is not available."""
+        Q blocks of the call; the gradient with an overlap (requested without density) also
+        leaves dF/dS for dFdS() and hf_forces_overlap()."""
         z, wf, wg = (_complex_pairs(fit[k]) for k in ("poles", "res_f", "res_g"))
         poly = np.array([fit["f0"], fit["g0"], fit["g1"]], dtype=np.float64)
         npol = z.shape[0]

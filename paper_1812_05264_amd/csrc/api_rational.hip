@@ -38,12 +38,13 @@ int cspmm(rfo_ctx *ctx, CxWork &w, const double *x, double *out, double zr, doub
 // x = 0), until |y - (H_hat - z) x| <= tol |y| for every column (checked on the
 // host every fourth iteration; later iterations only shrink the residuals).
 int cgls_solve(rfo_ctx *ctx, CxWork &w, double zr, double zi, double tol, int64_t max_iter,
-               bool first, int64_t *iters) {
+               bool first, int64_t *iters, const double *rhs = nullptr) {
   const int64_t n = ctx->n;
   const int sp = ctx->sp;
   const int G = rfo::cg_nparts(n), grid = w.ca.grid;
-  const uint64_t *sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
-  const double *rden = ctx->signs ? nullptr : P<double>(ctx->rden);
+  // right-hand side: the probes, or a dense real [n][sp] block when rhs is given
+  const uint64_t *sgn = rhs ? nullptr : ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
+  const double *rden = rhs ? rhs : ctx->signs ? nullptr : P<double>(ctx->rden);
   double *sc = w.sc;
   double *yy = sc, *qq = sc + 2 * sp, *ssn = sc + 3 * sp, *rr = sc + 4 * sp, *al = sc + 5 * sp,
          *be = sc + 6 * sp, *res_d = sc + 7 * sp;
@@ -112,8 +113,10 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   if (!ctx->has_r) return fail(ctx, RFO_E_STATE, "no probes: call rfo_set_probes first");
   if (ctx->prec != RFO_FP64)
     return fail(ctx, RFO_E_UNSUPPORTED, "the rational expansion runs in FP64 only");
-  if (ctx->has_s && dFdH_out)
-    return fail(ctx, RFO_E_UNSUPPORTED, "the rational free-energy gradient supports S = I only");
+  if (ctx->has_s && dFdH_out && density_out)
+    return fail(ctx, RFO_E_UNSUPPORTED,
+                "with an overlap, request the density and the gradient in separate calls (the Q blocks "
+                "and dF/dS share a buffer)");
   if (n_poles < 1 || n_poles > 4096) return fail(ctx, RFO_E_INVALID, "n_poles must be in [1, 4096]");
   if (!poles || !res_f || !res_g || !poly) return fail(ctx, RFO_E_INVALID, "NULL fit argument");
   if (!(tol > 0.0 && tol < 1.0)) return fail(ctx, RFO_E_INVALID, "tol must be in (0, 1)");
@@ -169,8 +172,10 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
     w.ca.grid = (int)std::max<int64_t>(8, grid / 8 * 8);
   }
   w.nparts = std::max(rfo::cg_nparts(n), w.ca.grid);
-  // planes: x, r, p, q, s (complex), the P r accumulator, and S r with an overlap
-  TRY(ensure(ctx, ctx->rat, (size_t)(ctx->has_s ? 12 : 11) * plane * sizeof(double)));
+  // planes: x, r, p, q, s (complex), the P r accumulator, and S r with an overlap; for the
+  // gradient with an overlap also the second solution (complex) and r
+  const bool grad_s = grad && ctx->has_s;
+  TRY(ensure(ctx, ctx->rat, (size_t)(grad_s ? 15 : ctx->has_s ? 12 : 11) * plane * sizeof(double)));
   if (ctx->has_s) {
     TRY(ensure(ctx, ctx->vec, 6 * pl.slot_bytes));  // CG work slots
     TRY(ensure_cg(ctx));
@@ -260,7 +265,36 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   sa.s_live = (int)ctx->s;
   const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
   ctx->has_grad = ctx->has_dens = ctx->has_q = false;
-  if (grad) {
+  ctx->grad_s = false;
+  // with an overlap: the second solves h_k = (H_hat - z_hat S)^{-1} S r (warm-started from
+  // the previous pole's, in X2) and r as a plane; the gradient terms are symmetric parts
+  // summed on the blocks on and above the diagonal (then mirrored)
+  double *X1 = w.x, *X2 = grad_s ? base + 12 * plane : nullptr, *Rp = grad_s ? base + 14 * plane : nullptr;
+  auto sym_term = [&](const double *X, const double *Y, double coef, double *G, int acc) -> int {
+    rfo::SddmmArgs b = sa;
+    b.nzlist = P<int64_t>(ctx->nz_up);
+    b.nlist = ctx->n_up;
+    b.sym = 1;
+    b.xbase = X;
+    b.ybase = Y;
+    b.first = 0.5 * coef;  // the symmetric kernel adds X Y^T + Y X^T
+    b.G = G;
+    b.accumulate = acc;
+    HIPCHK(rfo::launch_sddmm(0, b, ctx->stream));
+    return RFO_OK;
+  };
+  if (grad_s) {
+    TRY(ensure(ctx, ctx->G, gbytes));
+    TRY(ensure(ctx, ctx->GQ, gbytes));
+    HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 1.0, Rp, nullptr, ctx->stream));
+    // dF/dH starts at g1 r (S^{-1} r)^T; dF/dS at -g1 (S^{-1} H r)(S^{-1} r)^T, with
+    // S^{-1} H r by CG from H r = c q (in the real planes of r and s, free before the poles)
+    TRY(sym_term(Rp, SiR, poly[2], P<double>(ctx->G), 0));
+    HIPCHK(rfo::launch_cx_scale(w.q, w.r, plane, c, ctx->stream));
+    TRY(cg_solve(ctx, pl, ctx->vec, w.r, w.s));
+    TRY(sym_term(w.s, SiR, -poly[2], P<double>(ctx->GQ), 0));
+    HIPCHK(rfo::launch_cx_fill(sgn, rden, n, sp, 0.0, X2, X2 + plane, ctx->stream));  // h = 0
+  } else if (grad) {
     // the linear part of g: dF/dH = g1 sum_c w_c r_c r_c^T on the pattern
     TRY(ensure(ctx, ctx->G, gbytes));
     sa.xbase = w.x;
@@ -289,6 +323,7 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
   for (size_t t = 0; t < order.size(); ++t) {
     const int64_t k = order[t];
     const double zr = (poles[2 * k] - d) / c, zi = poles[2 * k + 1] / c;
+    w.x = X1;
     TRY(cgls_solve(ctx, w, zr, zi, tol, max_iter, t == 0, &iters[k]));
     // rho_k = (S r) . x_k, and P r += 2 Re[(w_k / c) x_k]
     const double wr = 2.0 * res_f[2 * k] / c, wi = 2.0 * res_f[2 * k + 1] / c;
@@ -297,7 +332,31 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
     HIPCHK(rfo::launch_colreduce(w.part, rfo::cg_nparts(n), sp, rho + (size_t)2 * k * sp, ctx->stream));
     HIPCHK(rfo::launch_colreduce(w.part2, rfo::cg_nparts(n), sp, rho + (size_t)(2 * k + 1) * sp,
                                  ctx->stream));
-    if (grad) {
+    if (grad_s) {
+      // h_k c = x2 = (H_hat - z_hat S)^{-1} S r; with g_k = x1 / c, h_k = x2 / c, z_k the pole:
+      //   dF/dH += -2 Re[tau_k h_k g_k^T],  dF/dS += 2 Re[tau_k (r g_k^T + z_k h_k g_k^T)],
+      // Re[t x2 x1^T] = tr (a2 a1^T - b2 b1^T) - ti (a2 b1^T + b2 a1^T)  (x = a + i b)
+      int64_t it2 = 0;  // counted in rfo_rational_stats; iterations_out keeps the solves with r
+      w.x = X2;
+      TRY(cgls_solve(ctx, w, zr, zi, tol, max_iter, t == 0, &it2, Sr));
+      w.x = X1;
+      const double *a1 = X1, *b1 = X1 + plane, *a2 = X2, *b2 = X2 + plane;
+      const double tr = res_g[2 * k], ti = res_g[2 * k + 1];
+      const double pr = poles[2 * k], pi = poles[2 * k + 1];
+      const double ur = tr * pr - ti * pi, ui = tr * pi + ti * pr;  // tau_k z_k
+      const double c2 = 2.0 / (c * c), c1 = 2.0 / c;
+      double *GH = P<double>(ctx->G), *GS = P<double>(ctx->GQ);
+      TRY(sym_term(a2, a1, -c2 * tr, GH, 1));
+      TRY(sym_term(b2, b1, c2 * tr, GH, 1));
+      TRY(sym_term(a2, b1, c2 * ti, GH, 1));
+      TRY(sym_term(b2, a1, c2 * ti, GH, 1));
+      TRY(sym_term(Rp, a1, c1 * tr, GS, 1));
+      TRY(sym_term(Rp, b1, -c1 * ti, GS, 1));
+      TRY(sym_term(a2, a1, c2 * ur, GS, 1));
+      TRY(sym_term(b2, b1, -c2 * ur, GS, 1));
+      TRY(sym_term(a2, b1, -c2 * ui, GS, 1));
+      TRY(sym_term(b2, a1, -c2 * ui, GS, 1));
+    } else if (grad) {
       // -2 Re[(tau_k / c^2) x_a x_b] = -2 Re t (xr xr - xi xi) + 2 Im t (xr xi + xi xr)
       const double tr = res_g[2 * k] / (c * c), ti = res_g[2 * k + 1] / (c * c);
       sa.accumulate = 1;
@@ -353,9 +412,16 @@ int rfo_rational_estimate(rfo_ctx *ctx, double mu, int64_t n_poles, const double
       ctx->has_q = true;
     }
   }
+  if (grad_s) {
+    HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
+                              P<double>(ctx->G), ctx->stream));
+    HIPCHK(rfo::launch_mirror(P<int64_t>(ctx->nz_low), ctx->n_low, P<int64_t>(ctx->tpos), ctx->bd,
+                              P<double>(ctx->GQ), ctx->stream));
+  }
   if (grad) {
     TRY(copy_out(ctx, dFdH_out, ctx->G.p, gbytes));
     ctx->has_grad = true;
+    ctx->grad_s = grad_s;
   }
   TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
   HIPCHK(hipStreamSynchronize(ctx->stream));

@@ -210,8 +210,41 @@ def test_rational_with_overlap_identity_probes_give_pencil_traces():
         assert np.max(np.abs(Q[z] - x["Q"][blk])) < 1e-10
 
 
-def test_rational_with_overlap_refuses_the_gradient():
-    banner("rational overlap gradient refused")
+@pytest.mark.parametrize("case", ["cu19_s72", "sc6_s100", "cu13_dense"])
+def test_rational_with_overlap_gradient_matches_oracle(case):
+    """dF/dH and dF/dS of the rational estimate with an overlap (Eq. rational_derivative with
+    dS, and the linear part of g; two solves per pole, r and S r), as symmetric parts, against
+    the oracle's sparse-LU solves; and the forces -(sum <dF/dH, dH/dR> + sum <dF/dS, dS/dR>)."""
+    banner(f"rational overlap gradient {case}")
+    w = None
+    if case == "cu19_s72":
+        (cl, H, S), s, T, mu, nodes = overlap_cu(19, 87), 72, 0.3, 0.2, 8
+        R = rademacher(H.n, s, config_id=88)
+    elif case == "sc6_s100":
+        (cl, H, S), s, T, mu, nodes = overlap_sc(6, 89), 100, 0.2, 0.1, 8
+        R = rademacher(H.n, s, config_id=90)
+    else:
+        (cl, H, S), s, T, mu, nodes = overlap_cu(13, 91), 37, 0.4, -0.1, 6
+        R = rademacher(H.n, s, config_id=92) * (1.0 + 0.25 * np.cos(np.arange(H.n)))[:, None]
+        w = np.linspace(0.5, 1.5, s) / s
+    fit = fit_for(H, nodes, T, mu)
+    eng = engine_or_skip()
+    load_overlap(eng, H, S, R, w)
+    g = eng.rational(mu, fit, tol=1e-13, max_iter=20000, gradient=True)
+    GS = eng.dFdS()
+    F, oH, oS = ra.gradient_overlap(H, S, R, fit, weights=w)
+    assert abs(g["F"] - F) <= TOL * max(1.0, abs(F)), (g["F"], F)
+    eH = check_blocks(g["dFdH"], oH, what="dF/dH")
+    eS = check_blocks(GS, oS, what="dF/dS")
+    print(f"{case}: dF/dH {eH:.2e}, dF/dS {eS:.2e} per block")
+    if cl is not None:
+        dH, dS = cl.dH_dR(), dS_dR(cl)
+        want = ofo.hf_forces(H, oH, dH) + ofo.hf_forces(H, oS, dS)
+        check_rows(eng.hf_forces_overlap(dH, dS), want, what="gradient forces")
+
+
+def test_rational_with_overlap_gradient_and_density_in_separate_calls():
+    banner("rational overlap gradient with density refused")
     import paper_1812_05264_amd as pkg
     _, H, S = overlap_cu(13, 86)
     R = rademacher(H.n, 8, config_id=86)
@@ -219,7 +252,7 @@ def test_rational_with_overlap_refuses_the_gradient():
     eng = engine_or_skip()
     load_overlap(eng, H, S, R)
     with pytest.raises(pkg.RfoError) as ei:
-        eng.rational(0.0, fit, gradient=True)
+        eng.rational(0.0, fit, gradient=True, density=True)
     assert ei.value.status == "RFO_E_UNSUPPORTED"
-    ok = eng.rational(0.0, fit, tol=1e-12)
-    assert np.isfinite(ok["F"])
+    ok = eng.rational(0.0, fit, tol=1e-12, gradient=True)
+    assert np.isfinite(ok["F"]) and np.isfinite(eng.dFdS()).all()
