@@ -76,9 +76,15 @@ def step_bytes(H, s, vt_bytes, mt_bytes, density, p=None):
 
 
 def kernel_digest():
+    """Digest of the step kernel's source: its file, the device helpers and its
+    argument struct (the rest of the internal header does not reach the kernel)."""
+    csrc = os.path.join(ROOT, "paper_1812_05264_amd", "csrc")
     h = hashlib.sha256()
-    for f in ("k_step.hip", "device_util.h", "rfo_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_1812_05264_amd", "csrc", f), "rb").read())
+    for f in ("k_step.hip", "device_util.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    hdr = open(os.path.join(csrc, "rfo_internal.h"), "rb").read()
+    i = hdr.index(b"struct StepArgs {")
+    h.update(hdr[i:hdr.index(b"};", i) + 2])
     return h.hexdigest()[:16]
 
 
