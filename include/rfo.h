@@ -351,7 +351,7 @@ int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
  *   RFO_TUNE_RPI            1x1: rows per wave iteration (1, 2, 7); 9x9: blocks per chunk (1, 2)
  *   RFO_TUNE_ROWS_PER_WG    block rows per scheduling unit of the step kernels (>= 1)
  *   RFO_TUNE_GRID           resident workgroups of the step kernels (>= 8, rounded to 8)
- *   RFO_TUNE_BF16_CHUNKS    BF16 steps: K chunks per iteration (1, 2, 4)
+ *   RFO_TUNE_BF16_CHUNKS    BF16 steps: K chunks of 32 rows per iteration (1, 2)
  *   RFO_TUNE_SDDMM_PPL      probes per lane of the vector-unit outer products (1, 2)
  *   RFO_TUNE_SDDMM_MFMA     0 keeps the BF16 segment gradient on the vector units (it then
  *                           reads the FP32 vectors instead of their BF16 copies)

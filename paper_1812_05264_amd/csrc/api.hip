@@ -171,28 +171,30 @@ int rfo_set_hamiltonian(rfo_ctx *ctx, int64_t n_block_rows, int block_dim, const
   }
   if (is_bf16(precision)) {
     // K chunks: block row I's blocks concatenated along K (9 rows each), cut into
-    // chunks of 16 K rows; K row k of the row is column c = k % 9 of block
+    // chunks of kKChunk K rows; K row k of the row is column c = k % 9 of block
     // nz = row_ptr[I] + k / 9
     const std::vector<int64_t> &rp = ctx->row_ptr_h;
     const std::vector<int32_t> &cl = ctx->col_h;
     if ((int64_t)ctx->nnzb * 9 >= ((int64_t)1 << 31) || ctx->n >= ((int64_t)1 << 31))
       return fail(ctx, RFO_E_UNSUPPORTED, "BF16 steps index rows with 32 bits");
     std::vector<int64_t> kp((size_t)ctx->nb + 1, 0);
-    for (int64_t I = 0; I < ctx->nb; ++I) kp[I + 1] = kp[I] + (9 * (rp[I + 1] - rp[I]) + 15) / 16;
+    constexpr int KC = rfo::kKChunk;
+    for (int64_t I = 0; I < ctx->nb; ++I) kp[I + 1] = kp[I] + (9 * (rp[I + 1] - rp[I]) + KC - 1) / KC;
     const int64_t nch = kp[ctx->nb];
-    std::vector<int32_t> kidx((size_t)nch * 16, -1), ksrc((size_t)nch * 16, -1);
+    std::vector<int32_t> kidx((size_t)nch * KC, -1), ksrc((size_t)nch * KC, -1);
     for (int64_t I = 0; I < ctx->nb; ++I)
       for (int64_t k = 0; k < 9 * (rp[I + 1] - rp[I]); ++k) {
         const int64_t nz = rp[I] + k / 9, c = k % 9;
-        kidx[(size_t)(kp[I] * 16 + k)] = (int32_t)((int64_t)cl[nz] * 9 + c);
-        ksrc[(size_t)(kp[I] * 16 + k)] = (int32_t)(nz * 9 + c);
+        kidx[(size_t)(kp[I] * KC + k)] = (int32_t)((int64_t)cl[nz] * 9 + c);
+        ksrc[(size_t)(kp[I] * KC + k)] = (int32_t)(nz * 9 + c);
       }
     ctx->n_chunks = nch;
     const size_t nq = (size_t)std::max<int64_t>(nch, 1);
     TRY(ensure(ctx, ctx->kc_ptr, kp.size() * sizeof(int64_t)));
-    TRY(ensure(ctx, ctx->kc_idx, nq * 16 * sizeof(int32_t)));
-    TRY(ensure(ctx, ctx->kc_src, nq * 16 * sizeof(int32_t)));
-    TRY(ensure(ctx, ctx->hbf16, nq * 36 * (precision == RFO_BF16X2 ? 16 : 8)));
+    TRY(ensure(ctx, ctx->kc_idx, nq * KC * sizeof(int32_t)));
+    TRY(ensure(ctx, ctx->kc_src, nq * KC * sizeof(int32_t)));
+    // 36 entries of eight BF16 values per chunk (twice that with the low parts)
+    TRY(ensure(ctx, ctx->hbf16, nq * 36 * (precision == RFO_BF16X2 ? 32 : 16)));
     HIPCHK(hipMemcpyAsync(ctx->kc_ptr.p, kp.data(), kp.size() * sizeof(int64_t), hipMemcpyHostToDevice,
                           ctx->stream));
     if (nch > 0) {
@@ -446,7 +448,7 @@ int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value) {
     case RFO_TUNE_RPI: ok = ok || value == 1 || value == 2 || value == 7; break;
     case RFO_TUNE_ROWS_PER_WG: ok = ok || (value >= 1 && value <= 4096); break;
     case RFO_TUNE_GRID: ok = ok || (value >= 8 && value <= (1 << 20)); break;
-    case RFO_TUNE_BF16_CHUNKS: ok = ok || value == 1 || value == 2 || value == 4; break;
+    case RFO_TUNE_BF16_CHUNKS: ok = ok || value == 1 || value == 2; break;
     case RFO_TUNE_SDDMM_PPL: ok = ok || value == 1 || value == 2; break;
     case RFO_TUNE_SDDMM_MFMA: ok = ok || value == 0 || value == 1; break;
     case RFO_TUNE_SDDMM_STEPS: ok = ok || (value >= 0 && value <= (1 << 20)); break;

@@ -227,10 +227,11 @@ inline Plan make_plan(const rfo_ctx *c) {
   pl.ntiles = 0;
   int occ = 1;
   if (is_bf16(c->prec)) {
-    // 4 MFMA column tiles (64 probes) per wave, 2 blocks per chunk: measured best
-    // (wider tiles or chunks cost more registers than the loads they add in flight)
+    // 4 MFMA column tiles (64 probes) per wave, one K chunk of 32 rows per
+    // iteration: measured best (wider tiles or more chunks cost more registers
+    // than the loads they add in flight)
     pl.ntiles = 4;
-    pl.rpi = 2;
+    pl.rpi = 1;
     pl.n_pt_step = c->sp / (16 * pl.ntiles);
     pl.rpi = (int)tuned(c, RFO_TUNE_BF16_CHUNKS, pl.rpi);
     occ = std::max(1, rfo::step_bf16_blocks_per_cu(pl.ntiles, pl.rpi, c->prec == RFO_BF16X2 ? 1 : 0));

@@ -2,13 +2,13 @@
 //
 // The block product Y_I = sum_J H_hat_IJ X_J is a dense 9x9 times 9 x (probes)
 // contraction per stored block (paper: block-sparse 9x9 matrix-vector work of
-// the Chebyshev recursion), so it maps onto v_mfma_f32_16x16x16_bf16:
-//   A (16 x 16, M x K) = the block H_hat_IJ, rows and columns 9..15 zero;
-//   B (16 x 16, K x N) = rows of X_J (k = input row 0..8, rows 9..15 zero) for
-//                        16 probe columns;
+// the Chebyshev recursion), so it maps onto CDNA4's v_mfma_f32_16x16x32_bf16:
+//   A (16 x 32, M x K) = H_hat_I* on 32 K rows, rows 9..15 zero;
+//   B (32 x 16, K x N) = 32 gathered rows of the X_J for 16 probe columns;
 //   D (16 x 16)        = FP32 accumulator of Y_I (rows 0..8 used).
-// Lane l supplies A[l%16][4(l/16)+kk], B[4(l/16)+kk][l%16] for kk < 4 and holds
-// D[4(l/16)+i][l%16] for i < 4.  A wave covers 16*NT probes as NT MFMA tiles;
+// Lane l supplies A[l%16][8(l/16)+kk], B[8(l/16)+kk][l%16] for kk < 8 and holds
+// D[4(l/16)+i][l%16] for i < 4 (checked on the device).  A wave covers 16*NT
+// probes as NT MFMA tiles;
 // column n of tile t is probe p0 + n*NT + t, so a lane reads and writes NT
 // consecutive probes of a row with one vector access.  Operands are BF16 (round
 // to nearest even); accumulation, the recurrence out = c1 D + c2 prev + beta r
@@ -18,11 +18,12 @@
 // the nine real rows of X_J are loaded (lanes of rows 9..15 load nothing).
 //
 // K is packed across the blocks of a block row: Y_I = [H_IJ1 H_IJ2 ...] [X_J1; X_J2; ...]
-// is one (9) x (9 nblk) times (9 nblk) x (probes) product, cut into chunks of 16
-// K rows, so that every K row of an MFMA is a real row of some X_J (only the last
-// chunk of a row has zero rows).  Per chunk, kc_idx lists the 16 gathered rows
-// J*9 + c and the A operands are pre-packed: entry g*9 + m (m < 9) holds the four
-// BF16 values H_hat_IJ[m][c] of K rows 4g .. 4g+3; lanes with m > 8 supply zeros.
+// is one (9) x (9 nblk) times (9 nblk) x (probes) product, cut into chunks of
+// kKChunk = 32 K rows, so that every K row of an MFMA is a real row of some X_J
+// (only the last chunk of a row has zero rows, which load nothing).  Per chunk,
+// kc_idx lists the 32 gathered rows J*9 + c and the A operands are pre-packed:
+// entry g*9 + m (m < 9) holds the eight BF16 values H_hat_IJ[m][c] of K rows
+// 8g .. 8g+7; lanes with m > 8 supply zeros.
 #include "device_util.h"
 #include "rfo_internal.h"
 
@@ -30,7 +31,7 @@ namespace rfo {
 
 namespace {
 
-typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef int i4 __attribute__((ext_vector_type(4)));
 
@@ -55,9 +56,8 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
   float *out = static_cast<float *>(a.out);
   unsigned short *outb = static_cast<unsigned short *>(a.outb);
   float *acc = static_cast<float *>(a.acc);
-  const uint2 *hpack = static_cast<const uint2 *>(a.hval);
-  // SPLIT: each pack entry holds the high and the low BF16 parts of its four values
-  const uint4 *hpack2 = static_cast<const uint4 *>(a.hval);
+  // SPLIT: each pack entry is followed by the low BF16 parts of its eight values
+  const uint4 *hpack = static_cast<const uint4 *>(a.hval);
   const i4 *kidx = reinterpret_cast<const i4 *>(a.kc_idx);
   const bool has_prev = a.c2 != 0.0;
   const bool add_r = a.beta != nullptr;
@@ -142,35 +142,31 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
       for (int t = 0; t < NT; ++t) d[t] = f4{0.f, 0.f, 0.f, 0.f};
       const int64_t q0 = sld(a.kc_ptr + I), q1 = sld(a.kc_ptr + I + 1);
       for (int64_t qc = q0; qc < q1; qc += U) {
-        s4 av[U], avl[U];
-        VecN<unsigned short, NT> xr[U][4];
+        bf8 av[U], avl[U];
+        VecN<unsigned short, NT> xr[U][8];
         const bool a_live = n < 9;
         const int a_idx = a_live ? g * 9 + n : 0;
+        const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const int64_t q = min(qc + u, q1 - 1);  // a repeated chunk is not accumulated
-          uint2 p, pl;
+          // every lane loads (a_idx is valid), then lanes of rows 9..15 take zeros
+          const int64_t e = q * 36 + a_idx;
+          const uint4 ph = hpack[SPLIT ? 2 * e : e];
+          av[u] = __builtin_bit_cast(bf8, a_live ? ph : zero4);
           if constexpr (SPLIT) {
-            const uint4 p4 = hpack2[q * 36 + a_idx];
-            p = make_uint2(p4.x, p4.y);
-            pl = make_uint2(p4.z, p4.w);
-          } else {
-            p = hpack[q * 36 + a_idx];
+            const uint4 pl = hpack[2 * e + 1];
+            avl[u] = __builtin_bit_cast(bf8, a_live ? pl : zero4);
           }
-          av[u] = a_live ? s4{(short)(p.x & 0xffff), (short)(p.x >> 16), (short)(p.y & 0xffff),
-                              (short)(p.y >> 16)}
-                         : s4{0, 0, 0, 0};
-          if constexpr (SPLIT)
-            avl[u] = a_live ? s4{(short)(pl.x & 0xffff), (short)(pl.x >> 16), (short)(pl.y & 0xffff),
-                                 (short)(pl.y >> 16)}
-                            : s4{0, 0, 0, 0};
-          // the chunk's 16 source rows (wave-uniform), four per lane group
-          const i4 k0 = sld(kidx + q * 4), k1 = sld(kidx + q * 4 + 1);
-          const i4 k2 = sld(kidx + q * 4 + 2), k3 = sld(kidx + q * 4 + 3);
-          const i4 kg = g == 0 ? k0 : (g == 1 ? k1 : (g == 2 ? k2 : k3));
-          const int src[4] = {kg.x, kg.y, kg.z, kg.w};
+          // the chunk's 32 source rows (wave-uniform), eight per lane group
+          i4 kq[8];
 #pragma unroll
-          for (int kk = 0; kk < 4; ++kk) {
+          for (int h = 0; h < 8; ++h) kq[h] = sld(kidx + q * 8 + h);
+          const i4 ka = g == 0 ? kq[0] : (g == 1 ? kq[2] : (g == 2 ? kq[4] : kq[6]));
+          const i4 kb = g == 0 ? kq[1] : (g == 1 ? kq[3] : (g == 2 ? kq[5] : kq[7]));
+          const int src[8] = {ka.x, ka.y, ka.z, ka.w, kb.x, kb.y, kb.z, kb.w};
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) {
             if (src[kk] >= 0 && live) {
               xr[u][kk] = ldv<unsigned short, NT>(xb + (int64_t)src[kk] * sp + cp);
             } else {
@@ -184,11 +180,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
           if (qc + u < q1) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
-              const s4 bv = s4{(short)xr[u][0].v[t], (short)xr[u][1].v[t], (short)xr[u][2].v[t],
-                               (short)xr[u][3].v[t]};
+              VecN<unsigned short, 8> b;
+#pragma unroll
+              for (int kk = 0; kk < 8; ++kk) b.v[kk] = xr[u][kk].v[t];
+              const bf8 bv = __builtin_bit_cast(bf8, b);
               // the low part first: the two products add in FP32 as (lo + hi) y
-              if constexpr (SPLIT) d[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(avl[u], bv, d[t], 0, 0, 0);
-              d[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[u], bv, d[t], 0, 0, 0);
+              if constexpr (SPLIT) d[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(avl[u], bv, d[t], 0, 0, 0);
+              d[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[u], bv, d[t], 0, 0, 0);
             }
           }
         }
@@ -280,15 +278,15 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 // probes, here symmetrized), for the BF16 steps: it reads the BF16 copies of the
 // segment's vectors (the operands the steps gather).  For a block (I, J) the sum
 // over the probes c is a 9 x K by K x 9 contraction, K = the probes, on
-// v_mfma_f32_16x16x16_bf16: A = X_I (M = the 9 rows, padded to 16), B = Y_J^T
+// v_mfma_f32_16x16x32_bf16: A = X_I (M = the 9 rows, padded to 16), B = Y_J^T
 // (N = the 9 rows of Y_J).  One wave owns a group of upper blocks of one block
 // row, so X_I and Y_I are loaded once for all of them; each block keeps a 16 x 16
 // FP32 tile (4 registers per lane), flushed into FP64 sums after every step t.
-// Lane l supplies A[l%16][4(l/16)..+3] and B[4(l/16)..+3][l%16] and holds
-// D[4(l/16)+i][l%16]; a lane loads 8 consecutive probes of a row with one
-// 16-byte access, the first four its K slots in one MFMA, the last four in the
-// next (the same probes in A and B).  Four waves per SIMD requested from the
-// compiler (125 VGPRs, no spills; the default took 150 and three waves).
+// Lane l supplies A[l%16][8(l/16)..+7] and B[8(l/16)..+7][l%16] and holds
+// D[4(l/16)+i][l%16] (layout checked on the device); a lane loads 8 consecutive
+// probes of a row with one 16-byte access, which are its eight K slots as they
+// stand, the same probes in A and B.  Four waves per SIMD requested from the
+// compiler (no spills; the default took three waves).
 // ---------------------------------------------------------------------------
 template <int GB>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k_sddmm_bf16(SddmmMfmaArgs a) {
@@ -350,19 +348,10 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) void k
 #pragma unroll
               for (int e = 0; e < 8; ++e) yj.v[e] = xj.v[e] = 0;
             }
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const s4 av = s4{(short)xa.v[4 * h], (short)xa.v[4 * h + 1], (short)xa.v[4 * h + 2],
-                               (short)xa.v[4 * h + 3]};
-              const s4 bv = s4{(short)yj.v[4 * h], (short)yj.v[4 * h + 1], (short)yj.v[4 * h + 2],
-                               (short)yj.v[4 * h + 3]};
-              const s4 av2 = s4{(short)ya.v[4 * h], (short)ya.v[4 * h + 1], (short)ya.v[4 * h + 2],
-                                (short)ya.v[4 * h + 3]};
-              const s4 bv2 = s4{(short)xj.v[4 * h], (short)xj.v[4 * h + 1], (short)xj.v[4 * h + 2],
-                                (short)xj.v[4 * h + 3]};
-              d[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, d[g], 0, 0, 0);
-              d[g] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av2, bv2, d[g], 0, 0, 0);
-            }
+            d[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, xa),
+                                                           __builtin_bit_cast(bf8, yj), d[g], 0, 0, 0);
+            d[g] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, ya),
+                                                           __builtin_bit_cast(bf8, xj), d[g], 0, 0, 0);
           }
         }
       }
@@ -397,36 +386,38 @@ hipError_t launch_sddmm_bf16(const SddmmMfmaArgs &a, hipStream_t s) {
   return hipGetLastError();
 }
 
-// Pack H_hat (FP64 [nnzb][9][9]) into the chunked A-operand layout above.
-// With split, entry e holds two uint2: the BF16 values hi = bf16(h) and then
-// lo = bf16(h - hi) (h the FP64 entry; hi + lo carries about 16 significant bits).
+// Pack H_hat (FP64 [nnzb][9][9]) into the chunked A-operand layout above: entry
+// e = 36 q + 9 g + m holds the eight BF16 values of K rows 8g .. 8g+7 of chunk q
+// for output row m (one uint4).  With split, entry e takes two uint4: the BF16
+// values hi = bf16(h) and then lo = bf16(h - hi) (h the FP64 entry; hi + lo
+// carries about 16 significant bits).
 __global__ __launch_bounds__(kWG) void k_pack_bf16(const double *__restrict__ hhat,
                                                    const int32_t *__restrict__ kc_src,
                                                    int64_t n_chunks, int split,
-                                                   uint2 *__restrict__ apack) {
+                                                   uint4 *__restrict__ apack) {
   const int64_t total = n_chunks * 36;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t q = e / 36;
     const int r = (int)(e - q * 36);
     const int gg = r / 9, m = r - gg * 9;
-    unsigned short v[4], vl[4];
+    unsigned v[8], vl[8];
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-      const int code = kc_src[q * 16 + 4 * gg + kk];
+    for (int kk = 0; kk < 8; ++kk) {
+      const int code = kc_src[q * kKChunk + 8 * gg + kk];
       const double h = code >= 0 ? hhat[(int64_t)(code / 9) * 81 + m * 9 + code % 9] : 0.0;
       v[kk] = bf16_bits((float)h);
-      const double hi = (double)__builtin_bit_cast(float, (unsigned)v[kk] << 16);
+      const double hi = (double)__builtin_bit_cast(float, v[kk] << 16);
       vl[kk] = bf16_bits((float)(h - hi));
     }
-    const uint2 hi2 = make_uint2((unsigned)v[0] | ((unsigned)v[1] << 16),
-                                 (unsigned)v[2] | ((unsigned)v[3] << 16));
+    const uint4 hi4 = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
+                                 v[6] | (v[7] << 16));
     if (split) {
-      apack[2 * e] = hi2;
-      apack[2 * e + 1] = make_uint2((unsigned)vl[0] | ((unsigned)vl[1] << 16),
-                                    (unsigned)vl[2] | ((unsigned)vl[3] << 16));
+      apack[2 * e] = hi4;
+      apack[2 * e + 1] = make_uint4(vl[0] | (vl[1] << 16), vl[2] | (vl[3] << 16), vl[4] | (vl[5] << 16),
+                                    vl[6] | (vl[7] << 16));
     } else {
-      apack[e] = hi2;
+      apack[e] = hi4;
     }
   }
 }
@@ -443,7 +434,6 @@ const void *select_bf16_t(int nt_tiles, int u, int mode) {
                        : (const void *)k_step9_bf16<T, UU, true, 0, SPLIT, PAD>;
   RFO_BF16_CASE(4, 1)
   RFO_BF16_CASE(4, 2)
-  RFO_BF16_CASE(4, 4)
 #undef RFO_BF16_CASE
   return nullptr;
 }
@@ -476,7 +466,7 @@ hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n
   int64_t blocks = (n_chunks * 36 + kWG - 1) / kWG;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_pack_bf16, dim3((unsigned)blocks), dim3(kWG), 0, s, hhat, kc_src, n_chunks, split,
-                     static_cast<uint2 *>(apack));
+                     static_cast<uint4 *>(apack));
   return hipGetLastError();
 }
 

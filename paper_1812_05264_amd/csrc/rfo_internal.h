@@ -34,7 +34,7 @@ struct StepArgs {
   const void *xb;          // BF16 steps: BF16 copy of y_k, the operand that is gathered
   void *outb;              // BF16 steps: BF16 copy of y_{k+1}, written with it
   const int64_t *kc_ptr;   // BF16 steps: first K chunk of each block row [nb + 1]
-  const int32_t *kc_idx;   // BF16 steps: per chunk, the 16 gathered rows J*9 + c (-1: zero row)
+  const int32_t *kc_idx;   // BF16 steps: per chunk, the kKChunk gathered rows J*9 + c (-1: zero row)
   const uint64_t *sgn;     // [n][sp/64] sign bits (bit 1 = +1), or nullptr
   const double *rden;      // [n][sp] dense probes, or nullptr
   double c1, c2;
@@ -96,14 +96,16 @@ struct InitArgs {
 hipError_t launch_init(int precision, const InitArgs &a, hipStream_t s);
 // Resident workgroups per CU of the step kernel variant (0 on error).
 int step_blocks_per_cu(int bd, int precision, int ppl, int rpi);
+// K rows per chunk of the BF16 MFMA step (the K of v_mfma_f32_16x16x32_bf16)
+constexpr int kKChunk = 32;
 // BF16 MFMA step for 9x9 blocks; a.hval holds the packed A operands
-// ([nnzb + kStepPad][27] uint2), a.n_pt counts tiles of 16 * nt_tiles probes.
+// ([n_chunks][36] uint4, two with split), a.n_pt counts tiles of 16 * nt_tiles probes.
 hipError_t launch_step_bf16(int nt_tiles, const StepArgs &a, hipStream_t s);
-int step_bf16_blocks_per_cu(int nt_tiles, int u, int split);  // u = blocks per chunk (a.rpi)
+int step_bf16_blocks_per_cu(int nt_tiles, int u, int split);  // u = K chunks per iteration (a.rpi)
 // A operands of the K-packed BF16 step: chunk q, lane group g, output row m holds
-// H_hat[nz][m][c] for the four K rows 4g..4g+3 of the chunk, whose source codes
-// kc_src[16 q + k] = nz * 9 + c (-1: zero) list the block and column of each K row.
-// split: each entry also carries the low BF16 parts bf16(h - bf16(h)).
+// H_hat[nz][m][c] for the eight K rows 8g..8g+7 of the chunk, whose source codes
+// kc_src[kKChunk q + k] = nz * 9 + c (-1: zero) list the block and column of each K row.
+// split: each entry is followed by the low BF16 parts bf16(h - bf16(h)).
 hipError_t launch_pack_bf16(const double *hhat, const int32_t *kc_src, int64_t n_chunks, int split,
                             void *apack, hipStream_t s);
 
