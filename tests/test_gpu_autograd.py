@@ -65,3 +65,37 @@ def test_forces_match_finite_differences_on_every_atom():
             worst = max(worst, abs(fd + f[a, d]))
     print(f"max |FD + force| over all atoms: {worst:.2e} eV/A")
     assert worst < 1e-6
+
+
+def test_autograd_forces_with_overlap():
+    """With an overlap, FermiFreeEnergyOverlap hands autograd dF~/dH and dF~/dS; composed
+    with torch-built H(R) and S(R), -dF~/dR must equal the library's contraction with
+    dH/dR and dS/dR and the oracle's gradient contracted the same way (Eq.
+    polynomial_response with dS != 0)."""
+    banner("autograd forces with an overlap")
+    torch = pytest.importorskip("torch")
+    eng = engine_or_skip()
+    from oracle import overlap as ov
+    from paper_1812_05264_amd.autograd import free_energy
+    from workloads import BSR
+    from workloads.overlap import dS_dR, overlap_torch, overlap_values, pencil_interval
+    cl = cu_cluster(19, config_id=14)
+    H0 = cl.bsr()
+    S = overlap_values(cl)
+    a, b = pencil_interval(H0, S)
+    H = BSR(H0.row_ptr, H0.col_idx, H0.values, 9, a, b)
+    R = rademacher(H.n, 8, config_id=605)
+    T, mu, p = 0.4, 0.1, 60
+    eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values, 9, a, b, "fp64")
+    eng.set_overlap(S, cg_tol=1e-14)
+    eng.set_probes(R)
+    pos = torch.tensor(cl.positions, dtype=torch.float64, device="cuda", requires_grad=True)
+    F = free_energy(cl.values_torch(pos), eng, T, mu, p, s_values=overlap_torch(cl, pos), cg_tol=1e-14)
+    F.backward()
+    f_auto = -pos.grad.cpu().numpy()
+    f_kernel = eng.hf_forces_overlap(cl.dH_dR(), dS_dR(cl))
+    Fo, oH, oS = ov.free_energy_gradient(H, S, R, T, mu, p)
+    f_oracle = ofo.hf_forces(H, oH, cl.dH_dR()) + ofo.hf_forces(H, oS, dS_dR(cl))
+    assert abs(F.item() - Fo) < 1e-10 * abs(Fo)
+    check_rows(f_auto, f_oracle, what="autograd forces with overlap")
+    check_rows(f_kernel, f_oracle, what="kernel forces with overlap")

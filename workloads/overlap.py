@@ -33,6 +33,24 @@ def overlap_values(cl, positions=None, sigma=SIGMA, lam=LAMBDA_S):
     return vals
 
 
+def overlap_torch(cl, positions, sigma=SIGMA, lam=LAMBDA_S):
+    """Same as overlap_values, written with torch ops so that autograd can differentiate it."""
+    import torch
+    pos = positions
+    pairs = torch.as_tensor(cl.pairs, device=pos.device)
+    d = pos[pairs[:, 0]] - pos[pairs[:, 1]]
+    r = torch.sqrt((d ** 2).sum(dim=1))
+    g = torch.as_tensor(_draws(cl), device=pos.device, dtype=pos.dtype)
+    upper = (sigma * torch.exp(-r / lam))[:, None, None] * g
+    kind = torch.as_tensor(cl.slot_kind, device=pos.device)
+    src = torch.as_tensor(cl.slot_src, device=pos.device)
+    out = torch.empty((cl.col_idx.shape[0], 9, 9), device=pos.device, dtype=pos.dtype)
+    out[kind == 0] = torch.eye(9, device=pos.device, dtype=pos.dtype)
+    out[kind == 1] = upper[src[kind == 1]]
+    out[kind == 2] = upper[src[kind == 2]].transpose(1, 2)
+    return out
+
+
 def dS_dR(cl, positions=None, sigma=SIGMA, lam=LAMBDA_S):
     """d S_IJ / d R_I [nnzb, 3, 9, 9] = -(1/lam) u_IJ S_IJ off the diagonal, 0 on it."""
     pos = cl.positions if positions is None else positions
