@@ -45,6 +45,7 @@ mean kernel time is roofline.mean_launch_us.
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -75,16 +76,26 @@ def step_bytes(H, s, vt_bytes, mt_bytes, density, p=None):
     return h + streams * vec + H.n * s / 8.0
 
 
-def kernel_digest():
-    """Digest of the step kernel's source: its file, the device helpers and its
-    argument struct (the rest of the internal header does not reach the kernel)."""
+def _code_only(src):
+    """Source text without comments and with whitespace collapsed: a digest over it
+    changes with the code, not with its comments."""
+    src = re.sub(rb"/\*.*?\*/", b" ", src, flags=re.S)
+    src = re.sub(rb"//[^\n]*", b" ", src)
+    return b" ".join(src.split())
+
+
+def kernel_digest(read=None):
+    """Digest of the step kernel's code: its file, the device helpers and its
+    argument struct (the rest of the internal header does not reach the kernel),
+    comments left out."""
     csrc = os.path.join(ROOT, "paper_1812_05264_amd", "csrc")
+    read = read or (lambda f: open(os.path.join(csrc, f), "rb").read())
     h = hashlib.sha256()
     for f in ("k_step.hip", "device_util.h"):
-        h.update(open(os.path.join(csrc, f), "rb").read())
-    hdr = open(os.path.join(csrc, "rfo_internal.h"), "rb").read()
+        h.update(_code_only(read(f)))
+    hdr = read("rfo_internal.h")
     i = hdr.index(b"struct StepArgs {")
-    h.update(hdr[i:hdr.index(b"};", i) + 2])
+    h.update(_code_only(hdr[i:hdr.index(b"};", i) + 2]))
     return h.hexdigest()[:16]
 
 
