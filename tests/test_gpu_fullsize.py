@@ -90,8 +90,13 @@ def test_cu4k_configuration(precision):
     assert abs(diag.sum() - g["N"]) < 1e-10 * abs(g["N"])
 
 
-def test_cu16k_configuration_fp64_and_bf16():
-    banner("cu16k full size: FP64 parity and BF16 error")
+def test_cu16k_configuration_all_precisions():
+    """cu16k moments in every step precision against the oracle fixture's per-probe traces.
+    FP64 is held to the parity bar; FP32 to the paper's accuracy target of 1e-6 eV/atom
+    (measured 3.5e-8 per probe); the matrix-core paths to regression bounds a few times their
+    measured per-probe errors (BF16 3.6e-4, BF16X2 7e-5 eV/atom in F or E), since they do not reach
+    the target (Ĥ's and the gathered vectors' BF16 rounding)."""
+    banner("cu16k full size: FP64 parity, FP32, BF16 and BF16X2 errors")
     fx, cfg, eng, H, cl, R = _cu_forward("cu16k", "fp64")
     cols = fx["columns"]
     g64 = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True)
@@ -100,15 +105,16 @@ def test_cu16k_configuration_fp64_and_bf16():
     for got, key in ((Nc, "N_c"), (Ec, "E_c"), (Fc, "F_c")):
         check_rows(np.reshape(got, (-1, 1)), np.reshape(fx[key], (-1, 1)), what=key)
         assert np.max(np.abs(np.asarray(got) - fx[key])) / n_at < 1e-6   # eV/atom, per probe
-    load_hamiltonian(eng, H, precision="bf16")
-    eng.set_probes(R)
-    g16 = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True)
-    Nb, Eb, Fb = per_probe_traces(g16["moments"][cols], cfg, H)
-    dF = np.max(np.abs(np.asarray(Fb) - fx["F_c"])) / n_at
-    dE = np.max(np.abs(np.asarray(Eb) - fx["E_c"])) / n_at
-    print(f"cu16k BF16 vs FP64 oracle, per probe: |dF| {dF:.2e} eV/atom, |dE| {dE:.2e} eV/atom; "
-          f"all-probe F {abs(g16['F'] - g64['F']) / n_at:.2e} eV/atom")
-    assert dF < 1e-2 and dE < 1e-2
+    for prec, bound in (("fp32", 1e-6), ("bf16", 2e-3), ("bf16x2", 3e-4)):
+        load_hamiltonian(eng, H, precision=prec)
+        eng.set_probes(R)
+        g = eng.fermi_moments(cfg.T, cfg.mu, cfg.n_terms, moments=True)
+        _, Eb, Fb = per_probe_traces(g["moments"][cols], cfg, H)
+        dF = np.max(np.abs(np.asarray(Fb) - fx["F_c"])) / n_at
+        dE = np.max(np.abs(np.asarray(Eb) - fx["E_c"])) / n_at
+        print(f"cu16k {prec} vs FP64 oracle, per probe: |dF| {dF:.2e} eV/atom, |dE| {dE:.2e} eV/atom; "
+              f"all-probe F {abs(g['F'] - g64['F']) / n_at:.2e} eV/atom")
+        assert dF < bound and dE < bound, prec
 
 
 @pytest.fixture(scope="module")
