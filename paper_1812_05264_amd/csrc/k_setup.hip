@@ -235,31 +235,39 @@ hipError_t launch_coefficients(double e_min, double e_max, double T, double mu, 
 
 // ---- moments ---------------------------------------------------------------------
 // flags bit 2: a moment exceeded its bound or is not finite.
-// One workgroup per (moment index, 64-probe chunk): the four waves sum strided
-// quarters of the row-group partials, then wave 0 adds the quarters in order.
-__global__ __launch_bounds__(kWG) void k_moment_reduce(const double *__restrict__ part, int ring,
-                                                       int64_t k0, int count, int n_rg, int sp,
-                                                       double *__restrict__ moments, int check,
-                                                       double tol, int *flags, int dbl) {
+// One workgroup of 16 waves per (moment index, 64-probe chunk): wave w sums the
+// partial rows g = w, w + 16, ... into four interleaved accumulators (so that
+// each lane keeps four loads in flight), adds them as (s0 + s1) + (s2 + s3), and
+// wave 0 adds the 16 wave sums in order.  The order is fixed, so the moments are
+// bitwise reproducible.
+constexpr int kRedWaves = 16;
+
+__global__ __launch_bounds__(64 * kRedWaves) void k_moment_reduce(const double *__restrict__ part, int ring,
+                                                                  int64_t k0, int count, int n_rg, int sp,
+                                                                  double *__restrict__ moments, int check,
+                                                                  double tol, int *flags, int dbl) {
   const int chunks = sp >> 6;
   const int d = blockIdx.x / chunks;
-  const int c = (blockIdx.x - d * chunks) * 64 + (threadIdx.x & 63);
+  const int lane = threadIdx.x & 63;
+  const int c = (blockIdx.x - d * chunks) * 64 + lane;
   const int wave = threadIdx.x >> 6;
   const int64_t k = k0 + d;
   const double *src = part + (int64_t)(k % ring) * n_rg * sp + c;
-  double s0 = 0.0, s1 = 0.0;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
   int g = wave;
-  for (; g + kWaves < n_rg; g += 2 * kWaves) {
-    s0 += src[(int64_t)g * sp];
-    s1 += src[(int64_t)(g + kWaves) * sp];
+  for (; g + 3 * kRedWaves < n_rg; g += 4 * kRedWaves) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s[u] += src[(int64_t)(g + u * kRedWaves) * sp];
   }
-  if (g < n_rg) s0 += src[(int64_t)g * sp];
-  __shared__ double red[kWaves][64];
-  red[wave][threadIdx.x & 63] = s0 + s1;
+#pragma unroll
+  for (int u = 0; u < 3; ++u)
+    if (g + u * kRedWaves < n_rg) s[u] += src[(int64_t)(g + u * kRedWaves) * sp];
+  __shared__ double red[kRedWaves][64];
+  red[wave][lane] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
   if (wave == 0) {
-    double sum = red[0][threadIdx.x];
-    for (int w = 1; w < kWaves; ++w) sum += red[w][threadIdx.x];
+    double sum = red[0][lane];
+    for (int w = 1; w < kRedWaves; ++w) sum += red[w][lane];
     // doubling: the partials hold <y_j, y_j> (k = 2j) or <y_j, y_{j-1}> (k = 2j-1);
     // T_2j = 2 T_j^2 - T_0 and T_2j-1 = 2 T_j T_j-1 - T_1 give the moment
     if (dbl && k >= 2) sum = 2.0 * sum - moments[(k & 1) * sp + c];
@@ -275,7 +283,7 @@ hipError_t launch_moment_reduce(const double *part, int ring, int64_t k0, int co
                                 int sp, double *moments, int check, double tol, int *flags,
                                 int dbl, hipStream_t s) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)(count * (sp >> 6))), dim3(kWG), 0, s, part,
+  hipLaunchKernelGGL(k_moment_reduce, dim3((unsigned)(count * (sp >> 6))), dim3(64 * kRedWaves), 0, s, part,
                      ring, k0, count, n_rg, sp, moments, check, tol, flags, dbl);
   return hipGetLastError();
 }
