@@ -543,7 +543,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--cpu-steps", type=int, default=12,
+    ap.add_argument("--cpu-steps", type=int, default=80,
                     help="oracle Chebyshev steps timed for the CPU baseline (0 = skip)")
     ap.add_argument("--energy-force", type=int, default=1)
     ap.add_argument("--ef-precisions", default="fp64,fp32,bf16,bf16x2")
