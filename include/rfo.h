@@ -371,6 +371,10 @@ int rfo_set_moment_doubling(rfo_ctx *ctx, int enabled);
  *   RFO_TUNE_ALT_SWEEP      1 (default): every other Chebyshev-step launch sweeps its rows
  *                           in the opposite order, so it first reads what the previous
  *                           launch touched last (0: always forward)
+ *   RFO_TUNE_ADJOINT_TAIL   1: rfo_energy_and_dEdH with the doubled moments keeps, within the
+ *                           memory budget above, the last vectors of its forward pass, so the
+ *                           top checkpoint segments are not replayed (the same gradient, bitwise;
+ *                           the context then holds up to the whole budget).  0 (default)
  * Geometry changes only the order of FP64 sums (rounding).  The segment gradient's step
  * groups, its matrix-core switch and the adjoint's probe batches change how G is summed
  * and so its rounding (and, for RFO_TUNE_SDDMM_MFMA = 0, which operands the BF16
@@ -392,7 +396,8 @@ typedef enum {
   RFO_TUNE_CPLX_GRID = 12,
   RFO_TUNE_ADJOINT_BYTES = 13,
   RFO_TUNE_ALT_SWEEP = 14,
-  RFO_TUNE_COUNT = 15
+  RFO_TUNE_ADJOINT_TAIL = 15,
+  RFO_TUNE_COUNT = 16
 } rfo_tuning;
 int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value);
 

@@ -352,7 +352,8 @@ class Engine:
 
     TUNING = {"ppl": 0, "rpi": 1, "rows_per_wg": 2, "grid": 3, "bf16_chunks": 4, "sddmm_ppl": 5,
               "sddmm_mfma": 6, "sddmm_steps": 7, "sddmm_steps_bf16": 8, "overlap": 9,
-              "cplx_ppl": 10, "cplx_rows": 11, "cplx_grid": 12, "adjoint_bytes": 13, "alt_sweep": 14}
+              "cplx_ppl": 10, "cplx_rows": 11, "cplx_grid": 12, "adjoint_bytes": 13, "alt_sweep": 14,
+              "adjoint_tail": 15}
 
     def set_tuning(self, key, value=-1):
         """Launch geometry / schedule of this context (rfo_set_tuning); -1 restores the default."""

@@ -459,6 +459,7 @@ int rfo_set_tuning(rfo_ctx *ctx, int key, int64_t value) {
     case RFO_TUNE_CPLX_GRID: ok = ok || (value >= 8 && value <= (1 << 20)); break;
     case RFO_TUNE_ADJOINT_BYTES: ok = ok || value >= 0; break;
     case RFO_TUNE_ALT_SWEEP: ok = ok || value == 0 || value == 1; break;
+    case RFO_TUNE_ADJOINT_TAIL: ok = ok || value == 0 || value == 1; break;
     default: break;
   }
   if (!ok) return fail(ctx, RFO_E_INVALID, "tuning value %lld out of range for key %d", (long long)value, key);

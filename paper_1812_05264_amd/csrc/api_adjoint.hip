@@ -15,7 +15,10 @@ namespace {
 //   dF~/dH_hat = z_1 y_0^T + 2 sum_{j=1}^{K-1} z_{j+1} y_j^T,
 // symmetrized (the doubled form is a function of H_hat^T as well as H_hat; the
 // gradient of F~ on symmetric matrices is the symmetric part).
-int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, size_t *n_events_out) {
+// tail_bytes: memory the call may add for a tail store (Checkpoints::tail): the last
+// vectors of the forward pass stay in place, so the top segments are not replayed.
+int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, size_t *n_events_out,
+                         size_t tail_bytes) {
   const int kp = kernel_precision(ctx);
   const int64_t K = p / 2;
   int64_t m = 2;
@@ -29,10 +32,18 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, si
   // so the serial schedule is the default and the overlap is taken on request.
   const bool overlap = Q > 1 && tuned(ctx, RFO_TUNE_OVERLAP, 0) != 0;
   const int n_sets = overlap ? 2 : 1;
-  // vector slots: n_sets x (ys [m + 2] | zs [m + 2]) | checkpoints [2 (Q - 1)]
+  // vector slots: n_sets x (ys [m + 2] | zs [m + 2]) | checkpoints [2 (Q - 1)] | tail
   const int64_t n_ys = m + 2, n_zs = m + 2, n_ck = Q > 1 ? 2 * (Q - 1) : 0;
   const int64_t set_slots = n_ys + n_zs;
-  TRY(ensure(ctx, ctx->vec, (size_t)(n_sets * set_slots + n_ck) * pl.slot_bytes));
+  // tail store: segments q >= q_s keep y_j, j in [q_s m, K], from the forward pass
+  int64_t q_s = Q;
+  if (!overlap && tail_bytes > 0) {
+    const int64_t fit = (int64_t)(tail_bytes / pl.slot_bytes);
+    while (q_s > 0 && K + 1 - (q_s - 1) * m <= fit) --q_s;
+  }
+  const int64_t tail_j0 = q_s * m, n_tail = q_s < Q ? K + 1 - tail_j0 : 0;
+  TRY(ensure(ctx, ctx->vec, (size_t)(n_sets * set_slots + n_ck + n_tail) * pl.slot_bytes));
+  char *tail = n_tail > 0 ? vec_at(ctx, pl, ctx->vec, n_sets * set_slots + n_ck) : nullptr;
   if (overlap) {
     if (!ctx->side) HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
     for (hipEvent_t *e : {&ctx->ev_rev, &ctx->ev_sd[0], &ctx->ev_sd[1]})
@@ -52,6 +63,8 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, si
   ck.m = m;
   ck.Q = Q;
   ck.store = &ckview;
+  ck.tail = tail;
+  ck.tail_j0 = tail_j0;
   TRY(run_forward(ctx, pl, p, ctx->vec, false, &ck, n_events_out, true));
   // source weights from beta^g (host copy of the device coefficients)
   std::vector<double> beta((size_t)p);
@@ -69,7 +82,12 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, si
 
   const size_t vb = pl.slot_bytes;
   int cur = 0;  // slot set of the segment being processed
-  auto ys = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, cur * set_slots + t); };
+  int64_t cur_j0 = 0;
+  bool cur_stored = false;  // the segment's y_j are in the tail store
+  auto ys = [&](int64_t t) {
+    return cur_stored ? tail + (size_t)(cur_j0 + t - tail_j0) * pl.slot_bytes
+                      : vec_at(ctx, pl, ctx->vec, cur * set_slots + t);
+  };
   auto zs = [&](int64_t t) { return vec_at(ctx, pl, ctx->vec, cur * set_slots + n_ys + t); };
   auto zs_of = [&](int set, int64_t t) { return vec_at(ctx, pl, ctx->vec, set * set_slots + n_ys + t); };
   auto cka = [&](int64_t q) { return vec_at(ctx, pl, ctx->vec, n_sets * set_slots + 2 * (q - 1)); };
@@ -82,6 +100,8 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, si
   for (int64_t q = Q - 1; q >= 0; --q) {
     const int64_t j0 = q * m, j1 = std::min(j0 + m, K), len = j1 - j0;
     cur = overlap ? (int)(q & 1) : 0;
+    cur_j0 = j0;
+    cur_stored = q >= q_s;
     if (sd_pending[cur]) {
       // the gradient of segment q + 2 read this set: wait before rewriting it
       HIPCHK(hipStreamWaitEvent(ctx->stream, ctx->ev_sd[cur], 0));
@@ -89,8 +109,10 @@ int energy_grad_doubling(rfo_ctx *ctx, const Plan &pl, int64_t p, bool g_acc, si
     }
     // replay y_j, j in [j0, min(j1 + 2, K + 1)), into ys[0 ..): the sources of
     // z_{j1} and z_{j1-1} need y_{j1} and y_{j1+1}
-    const int64_t rlen = std::min(j1 + 2, K + 1) - j0;
-    if (q == 0) {
+    const int64_t rlen = cur_stored ? 0 : std::min(j1 + 2, K + 1) - j0;
+    if (cur_stored) {
+      // kept by the forward pass
+    } else if (q == 0) {
       ia.out = ys(0);
       ia.scale = nullptr;
       ia.acc = nullptr;
@@ -599,10 +621,14 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
                 "is %zu (probe batches are not taken with an overlap)", (size_t)ctx->sp * per_probe, budget);
   double *obs = P<double>(ctx->small);
   if (width >= ctx->sp) {
-    TRY(ensure(ctx, ctx->vec, adjoint_slot_bytes(ctx, pl, p, dbl)));
+    const size_t need = adjoint_slot_bytes(ctx, pl, p, dbl);
+    if (!dbl) TRY(ensure(ctx, ctx->vec, need));  // the doubled form sizes its slots with the tail
     size_t n_events = 0;
+    // on request, what the budget leaves over keeps the last forward vectors (no
+    // replay of the top segments of the doubled adjoint)
+    const size_t tail = tuned(ctx, RFO_TUNE_ADJOINT_TAIL, 0) != 0 && budget > need ? budget - need : 0;
     TRY(ctx->has_s ? energy_grad_overlap(ctx, pl, p, &n_events)
-        : dbl      ? energy_grad_doubling(ctx, pl, p, false, &n_events)
+        : dbl      ? energy_grad_doubling(ctx, pl, p, false, &n_events, tail)
                    : energy_grad_direct(ctx, pl, p, false, &n_events));
     HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
                               ctx->sp, obs, ctx->stream));
@@ -669,7 +695,7 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
       TRY(ensure(ctx, ctx->ring, (size_t)bpl.ring * bpl.grid * sp_b * sizeof(double)));
       TRY(ensure(ctx, ctx->vec, adjoint_slot_bytes(ctx, bpl, p, dbl)));
       size_t n_events = 0;
-      TRY(dbl ? energy_grad_doubling(ctx, bpl, p, !first, &n_events)
+      TRY(dbl ? energy_grad_doubling(ctx, bpl, p, !first, &n_events, 0)
               : energy_grad_direct(ctx, bpl, p, !first, &n_events));
       HIPCHK(hipMemcpy2DAsync(P<double>(mom_all) + c0, all.sp * sizeof(double), ctx->moments.p,
                               sp_b * sizeof(double), s_b * sizeof(double), p,

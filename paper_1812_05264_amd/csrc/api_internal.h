@@ -410,6 +410,10 @@ inline int check_flags_and_finish(rfo_ctx *ctx, size_t n_events) {
 struct Checkpoints {
   int64_t m = 0, Q = 0;
   DevBuf *store = nullptr;  // 2 (Q - 1) vectors: [q-1][0] = y_{qm-1}, [q-1][1] = y_{qm}
+  // optional tail store: the forward pass writes y_j for j >= tail_j0 into
+  // consecutive vector slots from `tail` instead of its two working slots
+  char *tail = nullptr;
+  int64_t tail_j0 = 0;
 };
 
 inline int ensure_cg(rfo_ctx *ctx) {
@@ -482,6 +486,10 @@ inline int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bo
   char *A = vec_at(ctx, pl, bufs, 0);
   char *B = vec_at(ctx, pl, bufs, 1);
   void *accp = use_acc ? ctx->acc.p : nullptr;
+  char *tail = ck ? ck->tail : nullptr;
+  const int64_t tail_j0 = ck ? ck->tail_j0 : 0;
+  auto tail_at = [&](int64_t j) { return tail + (size_t)(j - tail_j0) * pl.slot_bytes; };
+  if (tail && tail_j0 == 0) A = tail_at(0);
 
   auto save = [&](int64_t k, const void *src) -> int {
     if (!ck || ck->Q < 2) return RFO_OK;
@@ -528,7 +536,7 @@ inline int run_forward(rfo_ctx *ctx, const Plan &pl, int64_t p, DevBuf &bufs, bo
       if (!e) return fail(ctx, RFO_E_DEVICE, "hipEventCreate failed");
       HIPCHK(hipEventRecord(e, ctx->stream));
     }
-    char *out = (k == 0) ? B : prev;
+    char *out = (tail && k + 1 >= tail_j0) ? tail_at(k + 1) : (k == 0) ? B : prev;
     sa.x = cur;
     sa.prev = prev;
     sa.out = out;

@@ -85,3 +85,39 @@ def test_cu16k_grad_1024_probes_run_in_batches():
     assert abs(big["F"] - F) <= 1e-12 * abs(F)
     check_blocks(big["dFdH"], G, 1e-12, what="1024 probes vs four 256-probe calls")
     assert np.max(np.abs(f_big.sum(axis=0))) < 1e-9 * np.max(np.abs(f_big))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_tail_store_equals_replay(prec):
+    """With RFO_TUNE_ADJOINT_TAIL, budget left over after the doubled adjoint's slots keeps the
+    last forward vectors, so the top checkpoint segments are not replayed: the same y_j either
+    way, so the gradient and F are bitwise those of the default (replaying) call, with no room
+    for a tail, a partial tail and every segment kept (cu55, 64 probes, 150 terms: 75 doubled
+    steps in 9 segments of 9)."""
+    banner(f"adjoint tail store {prec}")
+    import paper_1812_05264_amd as pkg
+    cl = cu_cluster(55, config_id=52)
+    H = cl.bsr()
+    R = rademacher(H.n, 64, config_id=902)
+    T, mu, p = 0.3, 0.2, 150
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H, precision=prec)
+    eng.set_probes(R)
+    eng.set_tuning("adjoint_bytes", 1)
+    with pytest.raises(pkg.RfoError) as err:
+        eng.energy_and_dEdH(T, mu, p)
+    need = int(re.search(r"needs (\d+) bytes of vectors for one batch of 64", str(err.value)).group(1))
+    eng.set_tuning("adjoint_bytes", -1)
+    out = {"replay": eng.energy_and_dEdH(T, mu, p)}
+    eng.set_tuning("adjoint_tail", 1)
+    for name, budget in (("none", need), ("partial", 2 * need), ("kept", -1)):
+        eng.set_tuning("adjoint_bytes", budget)
+        out[name] = eng.energy_and_dEdH(T, mu, p)
+    eng.set_tuning("adjoint_bytes", -1)
+    eng.set_tuning("adjoint_tail", -1)
+    for name in ("none", "partial", "kept"):
+        assert out[name]["F"] == out["replay"]["F"], name
+        assert np.array_equal(out[name]["dFdH"], out["replay"]["dFdH"]), name
+    if prec == "fp64":
+        o = est.estimate(H, R, T, mu, p, gradient=True)
+        check_blocks(out["kept"]["dFdH"], o["dFdH"], what="kept vs oracle")
