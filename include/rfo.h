@@ -181,6 +181,10 @@ int rfo_traces_at(rfo_ctx *ctx, double T, double mu, double *NEF_out);
  *   NEF_out   [3]  N, E, F of the forward pass (nullable)
  *   dFdH_out  [nnzb][bd][bd]  raw gradient G (nullable)
  * The gradient also stays on the device for rfo_hf_forces.
+ * Probe columns run in batches, each adding its sums to G, when the vectors of all
+ * probes exceed the memory budget (RFO_TUNE_ADJOINT_BYTES), and, in FP64 and FP32, when
+ * the last probe tile of 128 columns holds at most 64 real ones (that tile then runs
+ * 64 columns wide); batches change only the order of the FP64 sums.
  * With an overlap S (rfo_set_overlap) the derivative is that of F~ = sum_k beta_k
  * r^T T_k(H_hat S^{-1}) r (paper: Eq. polynomial_response), taken by the direct
  * recurrence (no moment doubling) with one conjugate-gradient solve per forward,

@@ -620,7 +620,18 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
     return fail(ctx, RFO_E_NOMEM, "the gradient with an overlap needs %zu bytes of vectors; the budget "
                 "is %zu (probe batches are not taken with an overlap)", (size_t)ctx->sp * per_probe, budget);
   double *obs = P<double>(ctx->small);
-  if (width >= ctx->sp) {
+  // Probe batches [c0, c0 + s_b): of `width` columns when the budget asks for them.
+  // Without that, a last VALU probe tile of 128 columns holding at most 64 real ones
+  // runs as a batch of its own, 64 columns wide: a tile costs about the same whatever
+  // part of it is live (the Hamiltonian is read and staged once per tile).
+  std::vector<std::pair<int64_t, int64_t>> batches;
+  if (width < ctx->sp) {
+    for (int64_t c0 = 0; c0 < ctx->s; c0 += width) batches.push_back({c0, std::min<int64_t>(width, ctx->s - c0)});
+  } else if (!ctx->has_s && !is_bf16(ctx->prec) && ctx->s > 128 && ctx->s % 128 != 0 && ctx->s % 128 <= 64) {
+    const int64_t r = ctx->s % 128;
+    batches = {{0, ctx->s - r}, {ctx->s - r, r}};
+  }
+  if (batches.empty()) {
     const size_t need = adjoint_slot_bytes(ctx, pl, p, dbl);
     if (!dbl) TRY(ensure(ctx, ctx->vec, need));  // the doubled form sizes its slots with the tail
     size_t n_events = 0;
@@ -634,8 +645,8 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
                               ctx->sp, obs, ctx->stream));
     TRY(check_flags_and_finish(ctx, n_events));
   } else {
-    // batches of `width` padded columns; the moments of every batch are gathered into
-    // the context's [p][sp] moments for the traces (and rfo_traces_at)
+    // the moments of every batch are gathered into the context's [p][sp] moments for
+    // the traces (and rfo_traces_at)
     ProbeState all{ctx->sgn, ctx->rden, ctx->w, ctx->s, ctx->sp, ctx->w_uniform};
     struct Restore {
       rfo_ctx *c;
@@ -659,8 +670,8 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
     HIPCHK(hipMemsetAsync(mom_all.p, 0, (size_t)p * all.sp * sizeof(double), ctx->stream));
     const size_t n = (size_t)ctx->n;
     bool first = true;
-    for (int64_t c0 = 0; c0 < all.s; c0 += width) {
-      const int64_t s_b = std::min<int64_t>(width, all.s - c0);
+    for (const auto &bt : batches) {
+      const int64_t c0 = bt.first, s_b = bt.second;
       const int sp_b = padded_probes(s_b);
       TRY(ensure(ctx, bw, (size_t)sp_b * sizeof(double)));
       std::vector<double> wb((size_t)sp_b, 0.0);

@@ -121,3 +121,34 @@ def test_tail_store_equals_replay(prec):
     if prec == "fp64":
         o = est.estimate(H, R, T, mu, p, gradient=True)
         check_blocks(out["kept"]["dFdH"], o["dFdH"], what="kept vs oracle")
+
+
+@pytest.mark.parametrize("dense", [False, True])
+@pytest.mark.parametrize("doubling", [True, False])
+def test_mostly_padding_last_tile_runs_as_its_own_batch(doubling, dense):
+    """A last probe tile of 128 columns with at most 64 real ones runs as a 64-column batch of
+    its own (s = 160: batches of 128 and 32 probes; dense: 150, 128 and 22): against the oracle
+    at the parity bar, with unequal weights."""
+    banner(f"last-tile batch doubling={doubling} dense={dense}")
+    cl = cu_cluster(55, config_id=53)
+    H = cl.bsr()
+    s = 150 if dense else 160
+    R = rademacher(H.n, s, config_id=903)
+    if dense:
+        R = R * (1.0 + 0.25 * np.cos(np.arange(H.n))[:, None])
+    w = np.linspace(0.5, 1.5, s) / s
+    T, mu, p = 0.3, 0.2, 97
+    eng = engine_or_skip()
+    load_hamiltonian(eng, H)
+    eng.set_probes(R, w)
+    eng.set_moment_doubling(doubling)
+    g = eng.energy_and_dEdH(T, mu, p)
+    f = eng.hf_forces(cl.dH_dR())
+    t = eng.traces_at(T, mu)
+    o = est.estimate(H, R, T, mu, p, weights=w, gradient=True)
+    for k in ("N", "E", "F"):
+        assert abs(g[k] - o[k]) <= 1e-10 * max(1.0, abs(o[k])), k
+        assert abs(t[k] - g[k]) <= 1e-13 * max(1.0, abs(g[k])), k
+    check_blocks(g["dFdH"], o["dFdH"], what="last-tile batch vs oracle")
+    from oracle import forces as ofo
+    check_rows(f, ofo.hf_forces(H, o["dFdH"], cl.dH_dR()), what="forces")
