@@ -581,8 +581,8 @@ def main():
                     help="time a 2 GiB device-to-device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: the hot path is measured on one GPU's share; "
-              "multi-GPU runs are not part of this build", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the hot path is measured on one GPU's share of "
+              "the probes; runs on several GPUs are not implemented", file=sys.stderr)
         sys.exit(2)
     if args.calibrate_copy:
         import torch

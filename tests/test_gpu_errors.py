@@ -1,4 +1,4 @@
-"""Error conventions of the C ABI, exercised through the binding on a GPU machine.
+"""Error conventions of the C ABI, exercised through the binding on a GPU.
 
 Every failure here is detected on the host or by a kernel's own checks; no test
 makes a kernel fault."""
