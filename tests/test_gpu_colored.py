@@ -22,14 +22,17 @@ def colored(cl, r_max, config_id):
     return colored_probes(c, 9, rademacher_signs(cl.n_atoms, 9, config_id=config_id))
 
 
+@pytest.mark.parametrize("r_max", [4.5, 5.5])
 @pytest.mark.parametrize("doubling", [True, False])
-def test_colored_probes_match_oracle(doubling):
-    banner(f"multi-color probes vs oracle doubling={doubling}")
+def test_colored_probes_match_oracle(doubling, r_max):
+    """r_max 4.5: 8 colours, 72 columns; 5.5: 16 colours, 144 columns, whose gradient runs
+    the last 16 columns as a probe batch of their own."""
+    banner(f"multi-color probes vs oracle doubling={doubling} r_max={r_max}")
     eng = engine_or_skip()
     eng.set_moment_doubling(doubling)
     cl = cu_cluster(55, config_id=44)
     H = cl.bsr()
-    R, w = colored(cl, 4.5, 44)
+    R, w = colored(cl, r_max, 44)
     load_hamiltonian(eng, H)
     eng.set_probes(R, w)
     T, mu, p = 0.3, 0.3, 90
