@@ -134,6 +134,9 @@ int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R,
  * from floor(p/2) steps instead: mu_2j = 2 y_j.y_j - mu_0 and
  * mu_2j-1 = 2 y_j.y_j-1 - mu_1 (T_2j = 2 T_j^2 - T_0, T_2j-1 = 2 T_j T_j-1 - T_1),
  * the same values up to rounding.
+ * In FP64 and FP32 without an overlap, a last probe tile of 128 columns holding at most
+ * 64 real probes runs as a batch of its own, 64 columns wide (the same values up to the
+ * order of FP64 sums).
  * Requires T > 0, finite mu, 1 <= n_terms <= 1048576.
  * Errors: RFO_E_STATE without H or probes; RFO_E_NUMERIC when a moment
  * exceeds ||r_c||^2 (relative slack 1e-6 in FP64, 1e-3 in FP32/BF16). */

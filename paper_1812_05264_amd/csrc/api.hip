@@ -327,12 +327,99 @@ int rfo_set_probes(rfo_ctx *ctx, int64_t n_probes, const double *R, const double
   return RFO_OK;
 }
 
+namespace {
+
+// Density blocks D (+)= sum_c w_c x_c r_c^T on H's pattern from the vectors x in
+// xbase (the density accumulator, or P r with an overlap) and the context's probes.
+int density_sddmm(rfo_ctx *ctx, const void *xbase, double *G, int accumulate) {
+  rfo::SddmmArgs a;
+  memset(&a, 0, sizeof(a));
+  a.brow = P<int64_t>(ctx->brow);
+  a.col = P<int32_t>(ctx->col);
+  a.nnzb = ctx->nnzb;
+  a.bd = ctx->bd;
+  a.sp = ctx->sp;
+  a.xbase = xbase;
+  a.ybase = nullptr;
+  a.sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
+  a.rden = ctx->signs ? nullptr : P<double>(ctx->rden);
+  a.w = P<double>(ctx->w);
+  a.count = 1;
+  a.scale = 1.0;
+  a.first = 1.0;
+  a.rest = 1.0;
+  a.G = G;
+  a.accumulate = accumulate;
+  a.nzlist = nullptr;
+  a.ppl = sddmm_ppl(ctx);
+  a.s_live = (int)ctx->s;
+  HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
+  return RFO_OK;
+}
+
+// rfo_fermi_moments over probe batches: the moments of every batch gathered into
+// the whole block's [p][sp] moments, the density blocks summed over the batches in
+// batch order.  (No overlap: last_tile_batches takes none with one.)
+int fermi_moments_batches(rfo_ctx *ctx, int64_t p, const std::vector<std::pair<int64_t, int64_t>> &batches,
+                          double *moments_out, double *NEF_out, double *density_out) {
+  const bool dens = density_out != nullptr;
+  const size_t gbytes = (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double);
+  if (dens) TRY(ensure(ctx, ctx->G, gbytes));
+  ProbeBatches pb(ctx);
+  DevBuf mom_all;
+  struct Release {
+    DevBuf &b;
+    ~Release() { release(b); }
+  } release_mom{mom_all};
+  TRY(ensure(ctx, mom_all, (size_t)p * pb.sp * sizeof(double)));
+  HIPCHK(hipMemsetAsync(mom_all.p, 0, (size_t)p * pb.sp * sizeof(double), ctx->stream));
+  bool first = true;
+  for (const auto &bt : batches) {
+    const int64_t c0 = bt.first, s_b = bt.second;
+    TRY(pb.select(c0, s_b));
+    const Plan bpl = make_plan(ctx);
+    TRY(ensure(ctx, ctx->ring, (size_t)bpl.ring * bpl.grid * ctx->sp * sizeof(double)));
+    TRY(ensure(ctx, ctx->vec, 2 * bpl.slot_bytes));
+    if (dens) TRY(ensure(ctx, ctx->acc, bpl.vec_elems * bpl.vt_bytes));
+    size_t n_events = 0;
+    TRY(run_forward(ctx, bpl, p, ctx->vec, dens, nullptr, &n_events, !dens && ctx->doubling));
+    HIPCHK(hipMemcpy2DAsync(P<double>(mom_all) + c0, pb.sp * sizeof(double), ctx->moments.p,
+                            ctx->sp * sizeof(double), s_b * sizeof(double), p, hipMemcpyDeviceToDevice,
+                            ctx->stream));
+    if (dens) TRY(density_sddmm(ctx, ctx->acc.p, P<double>(ctx->G), first ? 0 : 1));
+    TRY(check_flags_and_finish(ctx, n_events));
+    first = false;
+  }
+  pb.restore();
+  std::swap(ctx->moments, mom_all);
+  double *obs = P<double>(ctx->small);
+  HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
+                            ctx->sp, obs, ctx->stream));
+  ctx->has_q = false;
+  ctx->has_dens = dens;
+  if (dens) {
+    ctx->has_grad = false;  // G now holds the density
+    TRY(copy_out(ctx, density_out, ctx->G.p, gbytes));
+  }
+  TRY(copy_out(ctx, NEF_out, obs, 3 * sizeof(double)));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  TRY(copy_moments_out(ctx, p, moments_out));
+  ctx->mom_p = p;
+  return RFO_OK;
+}
+
+}  // namespace
+
 int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double *moments_out,
                       double *NEF_out, double *density_out) {
   if (!ctx) return RFO_E_INVALID;
   ctx->err.clear();
   Plan pl;
   TRY(prepare_call(ctx, T, mu, n_terms, pl));
+  // a last probe tile of 128 columns with at most 64 real probes runs as a batch
+  // of its own, 64 columns wide
+  const auto batches = last_tile_batches(ctx);
+  if (!batches.empty()) return fermi_moments_batches(ctx, n_terms, batches, moments_out, NEF_out, density_out);
   const bool dens = density_out != nullptr;
   // vector slots: y pair; with an overlap also t and the CG vectors r, p, q
   TRY(ensure(ctx, ctx->vec, (ctx->has_s ? 6 : 2) * pl.slot_bytes));
@@ -366,32 +453,9 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms, double
       TRY(cg_solve(ctx, pl, ctx->vec, vec_at(ctx, pl, ctx->vec, 0), qx));
       TRY(ensure(ctx, ctx->GQ, (size_t)ctx->nnzb * ctx->bd * ctx->bd * sizeof(double)));
     }
-    rfo::SddmmArgs a;
-    memset(&a, 0, sizeof(a));
-    a.brow = P<int64_t>(ctx->brow);
-    a.col = P<int32_t>(ctx->col);
-    a.nnzb = ctx->nnzb;
-    a.bd = ctx->bd;
-    a.sp = ctx->sp;
-    a.xbase = px;
-    a.ybase = nullptr;
-    a.sgn = ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
-    a.rden = ctx->signs ? nullptr : P<double>(ctx->rden);
-    a.w = P<double>(ctx->w);
-    a.count = 1;
-    a.scale = 1.0;
-    a.first = 1.0;
-    a.rest = 1.0;
-    a.G = P<double>(ctx->G);
-    a.accumulate = 0;
-    a.nzlist = nullptr;
-    a.ppl = sddmm_ppl(ctx);
-    a.s_live = (int)ctx->s;
-    HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
+    TRY(density_sddmm(ctx, px, P<double>(ctx->G), 0));
     if (qx) {
-      a.xbase = qx;
-      a.G = P<double>(ctx->GQ);
-      HIPCHK(rfo::launch_sddmm(kernel_precision(ctx), a, ctx->stream));
+      TRY(density_sddmm(ctx, qx, P<double>(ctx->GQ), 0));
       ctx->has_q = true;
     }
     ctx->has_grad = false;  // G now holds the density

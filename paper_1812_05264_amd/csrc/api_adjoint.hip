@@ -571,17 +571,6 @@ size_t adjoint_slot_bytes(const rfo_ctx *ctx, const Plan &pl, int64_t p, bool db
   return (size_t)std::max<int64_t>(slots, 2) * pl.slot_bytes;
 }
 
-// Padded width of a probe batch of s_real probes (the rule of rfo_set_probes).
-int padded_probes(int64_t s_real) { return s_real <= 64 ? 64 : (int)((s_real + 127) / 128 * 128); }
-
-// The probe state of a context, swapped for one batch of its probe columns and
-// restored afterwards.
-struct ProbeState {
-  DevBuf sgn, rden, w;
-  int64_t s;
-  int sp;
-  double w_uniform;
-};
 
 }  // namespace
 
@@ -627,9 +616,8 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   std::vector<std::pair<int64_t, int64_t>> batches;
   if (width < ctx->sp) {
     for (int64_t c0 = 0; c0 < ctx->s; c0 += width) batches.push_back({c0, std::min<int64_t>(width, ctx->s - c0)});
-  } else if (!ctx->has_s && !is_bf16(ctx->prec) && ctx->s > 128 && ctx->s % 128 != 0 && ctx->s % 128 <= 64) {
-    const int64_t r = ctx->s % 128;
-    batches = {{0, ctx->s - r}, {ctx->s - r, r}};
+  } else {
+    batches = last_tile_batches(ctx);
   }
   if (batches.empty()) {
     const size_t need = adjoint_slot_bytes(ctx, pl, p, dbl);
@@ -647,82 +635,34 @@ int rfo_energy_and_dEdH(rfo_ctx *ctx, double T, double mu, int64_t n_terms, doub
   } else {
     // the moments of every batch are gathered into the context's [p][sp] moments for
     // the traces (and rfo_traces_at)
-    ProbeState all{ctx->sgn, ctx->rden, ctx->w, ctx->s, ctx->sp, ctx->w_uniform};
-    struct Restore {
-      rfo_ctx *c;
-      const ProbeState &st;
-      DevBuf *bsgn, *brden, *bw, *bmom;
-      ~Restore() {
-        for (DevBuf *b : {bsgn, brden, bw, bmom}) release(*b);
-        c->sgn = st.sgn;
-        c->rden = st.rden;
-        c->w = st.w;
-        c->s = st.s;
-        c->sp = st.sp;
-        c->w_uniform = st.w_uniform;
-      }
-    };
-    DevBuf bsgn, brden, bw, mom_all;
-    Restore restore{ctx, all, &bsgn, &brden, &bw, &mom_all};
-    std::vector<double> w_h((size_t)all.sp);
-    HIPCHK(hipMemcpy(w_h.data(), all.w.p, w_h.size() * sizeof(double), hipMemcpyDeviceToHost));
-    TRY(ensure(ctx, mom_all, (size_t)p * all.sp * sizeof(double)));
-    HIPCHK(hipMemsetAsync(mom_all.p, 0, (size_t)p * all.sp * sizeof(double), ctx->stream));
-    const size_t n = (size_t)ctx->n;
+    ProbeBatches pb(ctx);
+    DevBuf mom_all;
+    struct Release {
+      DevBuf &b;
+      ~Release() { release(b); }
+    } release_mom{mom_all};
+    TRY(ensure(ctx, mom_all, (size_t)p * pb.sp * sizeof(double)));
+    HIPCHK(hipMemsetAsync(mom_all.p, 0, (size_t)p * pb.sp * sizeof(double), ctx->stream));
     bool first = true;
     for (const auto &bt : batches) {
       const int64_t c0 = bt.first, s_b = bt.second;
-      const int sp_b = padded_probes(s_b);
-      TRY(ensure(ctx, bw, (size_t)sp_b * sizeof(double)));
-      std::vector<double> wb((size_t)sp_b, 0.0);
-      for (int64_t c = 0; c < s_b; ++c) wb[c] = w_h[c0 + c];
-      HIPCHK(hipMemcpy(bw.p, wb.data(), wb.size() * sizeof(double), hipMemcpyHostToDevice));
-      if (all.sgn.p && !all.rden.p) {
-        // sign words [n][sp/64]: c0 is a multiple of 64, so a batch is whole words
-        TRY(ensure(ctx, bsgn, n * (sp_b / 64) * sizeof(uint64_t)));
-        HIPCHK(hipMemsetAsync(bsgn.p, 0, n * (sp_b / 64) * sizeof(uint64_t), ctx->stream));
-        const size_t words = (size_t)(s_b + 63) / 64;
-        HIPCHK(hipMemcpy2DAsync(bsgn.p, (sp_b / 64) * sizeof(uint64_t),
-                                P<uint64_t>(all.sgn) + c0 / 64, (all.sp / 64) * sizeof(uint64_t),
-                                words * sizeof(uint64_t), n, hipMemcpyDeviceToDevice, ctx->stream));
-        ctx->sgn = bsgn;
-        ctx->rden = DevBuf{};
-      } else {
-        TRY(ensure(ctx, brden, n * sp_b * sizeof(double)));
-        HIPCHK(hipMemsetAsync(brden.p, 0, n * sp_b * sizeof(double), ctx->stream));
-        HIPCHK(hipMemcpy2DAsync(brden.p, sp_b * sizeof(double), P<double>(all.rden) + c0,
-                                all.sp * sizeof(double), s_b * sizeof(double), n,
-                                hipMemcpyDeviceToDevice, ctx->stream));
-        ctx->rden = brden;
-        ctx->sgn = DevBuf{};
-      }
-      ctx->w = bw;
-      ctx->s = s_b;
-      ctx->sp = sp_b;
-      ctx->w_uniform = wb[0];
-      for (int64_t c = 1; c < s_b; ++c)
-        if (wb[c] != wb[0]) ctx->w_uniform = 0.0;
+      TRY(pb.select(c0, s_b));
+      const int sp_b = ctx->sp;
       const Plan bpl = make_plan(ctx);
       TRY(ensure(ctx, ctx->ring, (size_t)bpl.ring * bpl.grid * sp_b * sizeof(double)));
       TRY(ensure(ctx, ctx->vec, adjoint_slot_bytes(ctx, bpl, p, dbl)));
       size_t n_events = 0;
       TRY(dbl ? energy_grad_doubling(ctx, bpl, p, !first, &n_events, 0)
               : energy_grad_direct(ctx, bpl, p, !first, &n_events));
-      HIPCHK(hipMemcpy2DAsync(P<double>(mom_all) + c0, all.sp * sizeof(double), ctx->moments.p,
+      HIPCHK(hipMemcpy2DAsync(P<double>(mom_all) + c0, pb.sp * sizeof(double), ctx->moments.p,
                               sp_b * sizeof(double), s_b * sizeof(double), p,
                               hipMemcpyDeviceToDevice, ctx->stream));
       TRY(check_flags_and_finish(ctx, n_events));
       first = false;
     }
     // the gathered moments (padding columns zero) become the context's moments
+    pb.restore();
     std::swap(ctx->moments, mom_all);
-    release(mom_all);
-    ctx->sgn = all.sgn;
-    ctx->rden = all.rden;
-    ctx->w = all.w;
-    ctx->s = all.s;
-    ctx->sp = all.sp;
-    ctx->w_uniform = all.w_uniform;
     HIPCHK(rfo::launch_traces(P<double>(ctx->moments), P<double>(ctx->w), P<double>(ctx->coef), p,
                               ctx->sp, obs, ctx->stream));
   }

@@ -617,6 +617,84 @@ inline int prepare_call(rfo_ctx *ctx, double T, double mu, int64_t p, Plan &pl) 
   return RFO_OK;
 }
 
+// Padded width of a probe block of s_real probes (the rule of rfo_set_probes).
+inline int padded_probes(int64_t s_real) { return s_real <= 64 ? 64 : (int)((s_real + 127) / 128 * 128); }
+
+// Probe batches: select() swaps the context's probe block for its columns [c0, c0 + s_b)
+// (c0 a multiple of 64: whole sign words, or dense columns, copied into batch buffers,
+// with their weights); the whole block comes back with restore() and when this object
+// goes out of scope.
+struct ProbeBatches {
+  rfo_ctx *ctx;
+  DevBuf sgn, rden, w;  // the whole block (the context's buffers)
+  int64_t s;
+  int sp;
+  double w_uniform;
+  DevBuf bsgn, brden, bw;  // the selected batch
+  std::vector<double> w_h;
+  explicit ProbeBatches(rfo_ctx *c)
+      : ctx(c), sgn(c->sgn), rden(c->rden), w(c->w), s(c->s), sp(c->sp), w_uniform(c->w_uniform) {}
+  ProbeBatches(const ProbeBatches &) = delete;
+  ProbeBatches &operator=(const ProbeBatches &) = delete;
+  int select(int64_t c0, int64_t s_b) {
+    if (w_h.empty()) {
+      w_h.resize((size_t)sp);
+      HIPCHK(hipMemcpy(w_h.data(), w.p, w_h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    const int sp_b = padded_probes(s_b);
+    const size_t n = (size_t)ctx->n;
+    TRY(ensure(ctx, bw, (size_t)sp_b * sizeof(double)));
+    std::vector<double> wb((size_t)sp_b, 0.0);
+    for (int64_t c = 0; c < s_b; ++c) wb[(size_t)c] = w_h[(size_t)(c0 + c)];
+    HIPCHK(hipMemcpy(bw.p, wb.data(), wb.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (sgn.p && !rden.p) {
+      TRY(ensure(ctx, bsgn, n * (sp_b / 64) * sizeof(uint64_t)));
+      HIPCHK(hipMemsetAsync(bsgn.p, 0, n * (sp_b / 64) * sizeof(uint64_t), ctx->stream));
+      const size_t words = (size_t)(s_b + 63) / 64;
+      HIPCHK(hipMemcpy2DAsync(bsgn.p, (sp_b / 64) * sizeof(uint64_t), P<uint64_t>(sgn) + c0 / 64,
+                              (sp / 64) * sizeof(uint64_t), words * sizeof(uint64_t), n,
+                              hipMemcpyDeviceToDevice, ctx->stream));
+      ctx->sgn = bsgn;
+      ctx->rden = DevBuf{};
+    } else {
+      TRY(ensure(ctx, brden, n * sp_b * sizeof(double)));
+      HIPCHK(hipMemsetAsync(brden.p, 0, n * sp_b * sizeof(double), ctx->stream));
+      HIPCHK(hipMemcpy2DAsync(brden.p, sp_b * sizeof(double), P<double>(rden) + c0, sp * sizeof(double),
+                              s_b * sizeof(double), n, hipMemcpyDeviceToDevice, ctx->stream));
+      ctx->rden = brden;
+      ctx->sgn = DevBuf{};
+    }
+    ctx->w = bw;
+    ctx->s = s_b;
+    ctx->sp = sp_b;
+    ctx->w_uniform = wb[0];
+    for (int64_t c = 1; c < s_b; ++c)
+      if (wb[(size_t)c] != wb[0]) ctx->w_uniform = 0.0;
+    return RFO_OK;
+  }
+  void restore() {
+    ctx->sgn = sgn;
+    ctx->rden = rden;
+    ctx->w = w;
+    ctx->s = s;
+    ctx->sp = sp;
+    ctx->w_uniform = w_uniform;
+  }
+  ~ProbeBatches() {
+    for (DevBuf *b : {&bsgn, &brden, &bw}) release(*b);
+    restore();
+  }
+};
+
+// A last VALU probe tile of 128 columns that holds at most 64 real probes runs as a
+// batch of its own, 64 columns wide (a tile costs about the same whatever part of
+// it is live): the batches [0, s - r), [s - r, s), or none.
+inline std::vector<std::pair<int64_t, int64_t>> last_tile_batches(const rfo_ctx *c) {
+  if (c->has_s || is_bf16(c->prec) || c->s <= 128 || c->s % 128 == 0 || c->s % 128 > 64) return {};
+  const int64_t r = c->s % 128;
+  return {{0, c->s - r}, {c->s - r, r}};
+}
+
 inline int copy_moments_out(rfo_ctx *ctx, int64_t p, double *moments_out) {
   if (!moments_out) return RFO_OK;
   // internal [p][sp] -> caller [s][p]

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import estimator as est
-from tests.gpu_common import banner, check_blocks, check_rows, engine_or_skip, load_hamiltonian, rel
+from tests.gpu_common import banner, check_blocks, check_moments, check_rows, engine_or_skip, load_hamiltonian, rel
 from workloads import cu_cluster, rademacher
 from workloads.configs import CONFIGS, build_hamiltonian
 
@@ -127,8 +127,9 @@ def test_tail_store_equals_replay(prec):
 @pytest.mark.parametrize("doubling", [True, False])
 def test_mostly_padding_last_tile_runs_as_its_own_batch(doubling, dense):
     """A last probe tile of 128 columns with at most 64 real ones runs as a 64-column batch of
-    its own (s = 160: batches of 128 and 32 probes; dense: 150, 128 and 22): against the oracle
-    at the parity bar, with unequal weights."""
+    its own (s = 160: batches of 128 and 32 probes; dense: 150, 128 and 22), in the gradient
+    and in the moment and density calls: against the oracle at the parity bar, with unequal
+    weights."""
     banner(f"last-tile batch doubling={doubling} dense={dense}")
     cl = cu_cluster(55, config_id=53)
     H = cl.bsr()
@@ -145,10 +146,18 @@ def test_mostly_padding_last_tile_runs_as_its_own_batch(doubling, dense):
     g = eng.energy_and_dEdH(T, mu, p)
     f = eng.hf_forces(cl.dH_dR())
     t = eng.traces_at(T, mu)
-    o = est.estimate(H, R, T, mu, p, weights=w, gradient=True)
+    o = est.estimate(H, R, T, mu, p, weights=w, density=True, gradient=True)
     for k in ("N", "E", "F"):
         assert abs(g[k] - o[k]) <= 1e-10 * max(1.0, abs(o[k])), k
         assert abs(t[k] - g[k]) <= 1e-13 * max(1.0, abs(g[k])), k
     check_blocks(g["dFdH"], o["dFdH"], what="last-tile batch vs oracle")
     from oracle import forces as ofo
     check_rows(f, ofo.hf_forces(H, o["dFdH"], cl.dH_dR()), what="forces")
+    # the density and moment calls take the same batches
+    m = eng.fermi_moments(T, mu, p, moments=True, density=True)
+    check_moments(m["moments"], o["moments"])
+    check_blocks(m["density"], o["density"], what="density, last-tile batch")
+    for k in ("N", "E", "F"):
+        assert abs(m[k] - o[k]) <= 1e-10 * max(1.0, abs(o[k])), k
+    m2 = eng.fermi_moments(T, mu, p, moments=True)   # moment-only (doubled when enabled)
+    check_moments(m2["moments"], o["moments"])
