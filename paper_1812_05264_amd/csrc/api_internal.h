@@ -66,7 +66,7 @@ struct rfo_ctx {
   // nonorthogonal basis: overlap S on H's pattern, S^{-1} by conjugate gradients
   bool has_s = false, interval_given = false, has_q = false, has_dens = false;
   double cg_tol = 1e-13;
-  DevBuf s64, cg_part, cg_sc, GQ;
+  DevBuf s64, cg_part, cg_sc, cg_spart, GQ;
   double *cg_res_h = nullptr;
   int64_t cg_iters = 0, cg_solves = 0;
   int64_t mom_p = 0;     // moments of the last call still valid on the device (0 = none)
@@ -96,7 +96,7 @@ struct rfo_ctx {
     hipSetDevice(device);
     DevBuf *all[] = {&row_ptr, &col, &brow, &tpos, &hraw, &h64, &h32, &hbf16, &gscratch, &nz_up, &nz_low,
                      &kc_ptr, &kc_idx, &kc_src, &up_grp,
-                     &s64, &cg_part, &cg_sc, &GQ, &rat, &rat_part, &rat_sc, &rat_rho, &rat_coef,
+                     &s64, &cg_part, &cg_sc, &cg_spart, &GQ, &rat, &rat_part, &rat_sc, &rat_rho, &rat_coef,
                      &sgn, &rden, &w, &vec, &acc, &ring, &moments, &coef, &samples,
                      &costab, &small, &flags, &G, &dHdR, &forces};
     for (DevBuf *b : all)
@@ -437,6 +437,10 @@ inline int cg_solve(rfo_ctx *ctx, const Plan &pl, DevBuf &bufs, const void *y, v
   double *q = reinterpret_cast<double *>(vec_at(ctx, pl, bufs, 5));
   double *part = P<double>(ctx->cg_part), *sc = P<double>(ctx->cg_sc);
   double *res_d = sc + 6 * sp;
+  // the product's column partials of p . q (the step kernel's moment partials with p
+  // as the probe block): one pass over p and q fewer per iteration
+  TRY(ensure(ctx, ctx->cg_spart, (size_t)pl.grid * sp * sizeof(double)));
+  double *spart = P<double>(ctx->cg_spart);
   HIPCHK(rfo::launch_cg_init(static_cast<const double *>(y), static_cast<double *>(t), r, pv, n, sp,
                              part, sc, ctx->stream));
   rfo::StepArgs sa;
@@ -447,11 +451,14 @@ inline int cg_solve(rfo_ctx *ctx, const Plan &pl, DevBuf &bufs, const void *y, v
   sa.out = q;
   sa.c1 = 1.0;
   sa.c2 = 0.0;
+  sa.sgn = nullptr;
+  sa.rden = pv;
+  sa.part = spart;
   const double tol2 = ctx->cg_tol * ctx->cg_tol;
   const int max_it = 2000;
   for (int it = 1; it <= max_it; ++it) {
     HIPCHK(launch_any_step(ctx, pl, sa));
-    HIPCHK(rfo::launch_cg_alpha(pv, q, n, sp, part, sc, ctx->stream));
+    HIPCHK(rfo::launch_cg_alpha(spart, pl.grid, sp, sc, ctx->stream));
     HIPCHK(rfo::launch_cg_update(static_cast<double *>(t), r, pv, q, n, sp, part, sc, res_d,
                                  ctx->stream));
     ++ctx->cg_iters;

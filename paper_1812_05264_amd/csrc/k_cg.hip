@@ -52,19 +52,6 @@ __device__ __forceinline__ void row_range(int64_t n, int64_t &lo, int64_t &hi) {
 
 }  // namespace
 
-// part[b][c] = sum over this workgroup's rows of a[i][c] * b[i][c]
-__global__ __launch_bounds__(kWG) void k_coldot(const double *__restrict__ a,
-                                                const double *__restrict__ bv, int64_t n, int sp,
-                                                double *__restrict__ part) {
-  int64_t lo, hi;
-  row_range(n, lo, hi);
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
-    double s = 0.0;
-    for (int64_t i = lo; i < hi; ++i) s = fma(a[i * sp + c], bv[i * sp + c], s);
-    part[(int64_t)blockIdx.x * sp + c] = s;
-  }
-}
-
 // out[c] = sum_b part[b][c].  A workgroup of kRW waves takes 64 columns; wave w
 // sums the rows b = w, w + kRW, ... in increasing order and the kRW wave sums
 // are then added in wave order, so the result is bitwise reproducible.
@@ -194,11 +181,8 @@ hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int6
   return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(const double *p, const double *q, int64_t n, int sp, double *part,
-                           double *sc, hipStream_t s) {
-  const int G = cg_parts(n);
-  hipLaunchKernelGGL(k_coldot, dim3(G), dim3(kWG), 0, s, p, q, n, sp, part);
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp,
+hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, nparts, sp,
                      sc + 2 * sp);
   hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 1, (double *)nullptr);
   return hipGetLastError();

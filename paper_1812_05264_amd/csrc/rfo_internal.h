@@ -218,9 +218,9 @@ int cg_nparts(int64_t n);
 // t = 0, r = p = y, yy = rr = |y_c|^2
 hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int64_t n, int sp,
                           double *part, double *sc, hipStream_t s);
-// alpha_c = rr_c / (p_c . q_c), q = S p computed before
-hipError_t launch_cg_alpha(const double *p, const double *q, int64_t n, int sp, double *part,
-                           double *sc, hipStream_t s);
+// alpha_c = rr_c / (p_c . q_c) from the column partials of p . q that the product
+// q = S p left in part [nparts][sp] (its moment partials with p as the probe block)
+hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, hipStream_t s);
 // t += alpha p, r -= alpha q, beta = |r|^2 / rr, rr = |r|^2, p = r + beta p, *resmax
 hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, int64_t n, int sp,
                             double *part, double *sc, double *resmax, hipStream_t s);
