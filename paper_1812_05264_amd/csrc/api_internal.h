@@ -458,7 +458,7 @@ inline int cg_solve(rfo_ctx *ctx, const Plan &pl, DevBuf &bufs, const void *y, v
   const int max_it = 2000;
   for (int it = 1; it <= max_it; ++it) {
     HIPCHK(launch_any_step(ctx, pl, sa));
-    HIPCHK(rfo::launch_cg_alpha(spart, pl.grid, sp, sc, ctx->stream));
+    HIPCHK(rfo::launch_cg_alpha(spart, pl.grid, sp, sc, res_d, ctx->stream));
     HIPCHK(rfo::launch_cg_update(static_cast<double *>(t), r, pv, q, n, sp, part, sc, res_d,
                                  ctx->stream));
     ++ctx->cg_iters;

@@ -76,6 +76,16 @@ __global__ __launch_bounds__(64 * kRW) void k_colreduce(const double *__restrict
   }
 }
 
+// The row-range kernels below split a workgroup's threads into R = 256 / C row lanes of
+// C columns (C = 64, 128 or 256, the widest that divides sp): rows lo + rl, lo + rl + R,
+// ... for the C columns c0 + cl, column chunk by column chunk; the R row lanes of a
+// column are then added in row-lane order, so the partials are bitwise reproducible.
+__device__ __forceinline__ int cg_cols(int sp) {
+  int C = 64;
+  while (C < kWG && sp % (2 * C) == 0) C *= 2;
+  return C;
+}
+
 // t = 0, r = y, p = y, part = column partials of y . y
 __global__ __launch_bounds__(kWG) void k_cg_init(const double *__restrict__ y,
                                                  double *__restrict__ t, double *__restrict__ r,
@@ -83,9 +93,13 @@ __global__ __launch_bounds__(kWG) void k_cg_init(const double *__restrict__ y,
                                                  double *__restrict__ part) {
   int64_t lo, hi;
   row_range(n, lo, hi);
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+  const int C = cg_cols(sp), R = kWG / C;
+  const int cl = threadIdx.x % C, rl = threadIdx.x / C;
+  __shared__ double red[kWG];
+  for (int c0 = 0; c0 < sp; c0 += C) {
+    const int c = c0 + cl;
     double s = 0.0;
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t i = lo + rl; i < hi; i += R) {
       const int64_t e = i * sp + c;
       const double v = y[e];
       t[e] = 0.0;
@@ -93,7 +107,14 @@ __global__ __launch_bounds__(kWG) void k_cg_init(const double *__restrict__ y,
       p[e] = v;
       s = fma(v, v, s);
     }
-    part[(int64_t)blockIdx.x * sp + c] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (rl == 0) {
+      double a = red[cl];
+      for (int q = 1; q < R; ++q) a += red[q * C + cl];
+      part[(int64_t)blockIdx.x * sp + c] = a;
+    }
+    __syncthreads();
   }
 }
 
@@ -105,59 +126,85 @@ __global__ __launch_bounds__(kWG) void k_cg_update(double *__restrict__ t, doubl
                                                    int sp, double *__restrict__ part) {
   int64_t lo, hi;
   row_range(n, lo, hi);
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
+  const int C = cg_cols(sp), R = kWG / C;
+  const int cl = threadIdx.x % C, rl = threadIdx.x / C;
+  __shared__ double red[kWG];
+  for (int c0 = 0; c0 < sp; c0 += C) {
+    const int c = c0 + cl;
     const double al = alpha[c];
     double s = 0.0;
-    for (int64_t i = lo; i < hi; ++i) {
+    for (int64_t i = lo + rl; i < hi; i += R) {
       const int64_t e = i * sp + c;
       t[e] = fma(al, p[e], t[e]);
       const double rn = fma(-al, q[e], r[e]);
       r[e] = rn;
       s = fma(rn, rn, s);
     }
-    part[(int64_t)blockIdx.x * sp + c] = s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (rl == 0) {
+      double a = red[cl];
+      for (int w = 1; w < R; ++w) a += red[w * C + cl];
+      part[(int64_t)blockIdx.x * sp + c] = a;
+    }
+    __syncthreads();
   }
 }
 
-// p = r + beta_c p
+// p = r + beta_c p.  The grid's thread count is a multiple of sp, so a thread's column
+// stays the same over its grid-stride loop.
 __global__ __launch_bounds__(kWG) void k_cg_direction(const double *__restrict__ r,
                                                       double *__restrict__ p,
                                                       const double *__restrict__ beta, int64_t n,
                                                       int sp) {
   const int64_t total = n * sp;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x)
-    p[e] = fma(beta[e % sp], p[e], r[e]);
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double be = beta[e0 % sp];
+  for (int64_t e = e0; e < total; e += (int64_t)gridDim.x * blockDim.x) p[e] = fma(be, p[e], r[e]);
 }
 
-// Per-column CG scalars (one workgroup).  sc = [yy | rr | pq | rrn | alpha | beta] of sp each.
-// mode 0: rr = yy (start);  mode 1: alpha = rr / pq;  mode 2: beta = rrn / rr, rr = rrn and
-// *resmax = max_c rrn / yy over columns with yy > 0 (columns with rr = 0 stay at alpha = beta = 0).
-__global__ __launch_bounds__(kWG) void k_cg_scalars(double *__restrict__ sc, int sp, int mode,
-                                                    double *__restrict__ resmax) {
+// Column sums of part [nparts][sp] (as k_colreduce: wave w adds rows w, w + kRW, ...,
+// then the wave sums in wave order), then the per-column CG scalars of `mode` on
+// sc = [yy | rr | pq | rrn | alpha | beta] of sp each:
+//   mode 0: yy = rr = the sums (start);
+//   mode 1: pq = the sums, alpha = rr / pq, and *resmax = 0 for the coming mode 2;
+//   mode 2: rrn = the sums, beta = rrn / rr, rr = rrn, and *resmax = max_c rrn / yy over
+//           columns with yy > 0, by an integer max on the bit patterns (non-negative
+//           doubles order as their bits, and a NaN ends above every finite value).
+// Columns with rr = 0 keep alpha = beta = 0.
+__global__ __launch_bounds__(64 * kRW) void k_cg_reduce(const double *__restrict__ part, int nparts,
+                                                        int sp, double *__restrict__ sc, int mode,
+                                                        double *__restrict__ resmax) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int c = blockIdx.x * 64 + lane;
+  __shared__ double red[kRW][64];
+  double s = 0.0;
+  if (c < sp) {
+#pragma unroll 8
+    for (int b = wave; b < nparts; b += kRW) s += part[(int64_t)b * sp + c];
+  }
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave != 0) return;
   double *yy = sc, *rr = sc + sp, *pq = sc + 2 * sp, *rrn = sc + 3 * sp, *al = sc + 4 * sp,
          *be = sc + 5 * sp;
-  double m = 0.0;
-  for (int c = threadIdx.x; c < sp; c += blockDim.x) {
-    if (mode == 0) {
-      rr[c] = yy[c];
-    } else if (mode == 1) {
-      al[c] = (rr[c] > 0.0 && pq[c] != 0.0) ? rr[c] / pq[c] : 0.0;
-    } else {
-      be[c] = rr[c] > 0.0 ? rrn[c] / rr[c] : 0.0;
-      rr[c] = rrn[c];
-      if (yy[c] > 0.0) m = fmax(m, rrn[c] / yy[c]);
-    }
-  }
-  if (mode != 2) return;
-  m = wave_max(m);
-  __shared__ double red[kWaves];
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double t = red[0];
-    for (int w = 1; w < kWaves; ++w) t = fmax(t, red[w]);
-    *resmax = t;
+  if (mode == 1 && blockIdx.x == 0 && lane == 0) *resmax = 0.0;
+  if (c >= sp) return;
+  double v = red[0][lane];
+  for (int w = 1; w < kRW; ++w) v += red[w][lane];
+  if (mode == 0) {
+    yy[c] = v;
+    rr[c] = v;
+  } else if (mode == 1) {
+    pq[c] = v;
+    al[c] = (rr[c] > 0.0 && v != 0.0) ? rr[c] / v : 0.0;
+  } else {
+    rrn[c] = v;
+    be[c] = rr[c] > 0.0 ? v / rr[c] : 0.0;
+    rr[c] = v;
+    if (yy[c] > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long *>(resmax),
+                (unsigned long long)__double_as_longlong(v / yy[c]));
   }
 }
 
@@ -174,29 +221,34 @@ hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out,
 
 hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int64_t n, int sp,
                           double *part, double *sc, hipStream_t s) {
+  if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(kWG), 0, s, y, t, r, p, n, sp, part);
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp, sc);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 0, (double *)nullptr);
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp, sc, 0,
+                     (double *)nullptr);
   return hipGetLastError();
 }
 
-hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, hipStream_t s) {
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, nparts, sp,
-                     sc + 2 * sp);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 1, (double *)nullptr);
+hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, double *resmax,
+                           hipStream_t s) {
+  if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, nparts, sp, sc, 1,
+                     resmax);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, int64_t n, int sp,
                             double *part, double *sc, double *resmax, hipStream_t s) {
+  if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kWG), 0, s, t, r, p, q, sc + 4 * sp, n, sp, part);
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp,
-                     sc + 3 * sp);
-  hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, 2, resmax);
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp, sc, 2,
+                     resmax);
+  // blocks a multiple of sp / 64, so blocks * kWG is a multiple of sp
+  const int64_t unit = sp / 64;
   int64_t blocks = (n * sp + kWG - 1) / kWG;
   if (blocks > 65536) blocks = 65536;
+  blocks = (blocks + unit - 1) / unit * unit;
   hipLaunchKernelGGL(k_cg_direction, dim3((unsigned)blocks), dim3(kWG), 0, s, r, p, sc + 5 * sp, n,
                      sp);
   return hipGetLastError();

@@ -210,6 +210,7 @@ hipError_t launch_forces(const int64_t *row_ptr, const int64_t *tpos,
 // Nonorthogonal basis: H_hat with S, and conjugate gradients for S t = y per
 // probe column.  sc holds [yy | rr | pq | rrn | alpha | beta] (sp each), part
 // [cg_nparts(n)][sp] column partials, resmax the largest rrn / yy after an update.
+// sp must be a positive multiple of 64 (hipErrorInvalidValue otherwise).
 // ---------------------------------------------------------------------------
 hipError_t launch_map_overlap(const double *h, const double *s, const int64_t *tpos, int64_t nnzb,
                               int bd, double e_min, double e_max, double *hhat, int *flags,
@@ -219,8 +220,10 @@ int cg_nparts(int64_t n);
 hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int64_t n, int sp,
                           double *part, double *sc, hipStream_t s);
 // alpha_c = rr_c / (p_c . q_c) from the column partials of p . q that the product
-// q = S p left in part [nparts][sp] (its moment partials with p as the probe block)
-hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, hipStream_t s);
+// q = S p left in part [nparts][sp] (its moment partials with p as the probe block);
+// sets *resmax = 0 for the update that follows
+hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, double *resmax,
+                           hipStream_t s);
 // t += alpha p, r -= alpha q, beta = |r|^2 / rr, rr = |r|^2, p = r + beta p, *resmax
 hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, int64_t n, int sp,
                             double *part, double *sc, double *resmax, hipStream_t s);
