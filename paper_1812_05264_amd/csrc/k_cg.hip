@@ -163,8 +163,7 @@ __global__ __launch_bounds__(kWG) void k_cg_direction(const double *__restrict__
   for (int64_t e = e0; e < total; e += (int64_t)gridDim.x * blockDim.x) p[e] = fma(be, p[e], r[e]);
 }
 
-// Column sums of part [nparts][sp] (as k_colreduce: wave w adds rows w, w + kRW, ...,
-// then the wave sums in wave order), then the per-column CG scalars of `mode` on
+// Column sums of part [nparts][sp], then the per-column CG scalars of `mode` on
 // sc = [yy | rr | pq | rrn | alpha | beta] of sp each:
 //   mode 0: yy = rr = the sums (start);
 //   mode 1: pq = the sums, alpha = rr / pq, and *resmax = 0 for the coming mode 2;
@@ -172,26 +171,34 @@ __global__ __launch_bounds__(kWG) void k_cg_direction(const double *__restrict__
 //           columns with yy > 0, by an integer max on the bit patterns (non-negative
 //           doubles order as their bits, and a NaN ends above every finite value).
 // Columns with rr = 0 keep alpha = beta = 0.
+// A workgroup of kRW waves takes kRedCols columns: lane l of wave w adds, for column
+// l % kRedCols, the rows h, h + kRedPh, ... of phase h = w * (64 / kRedCols) + l / kRedCols
+// in order, and the kRedPh phase sums are then added in phase order, so the sums are
+// bitwise reproducible (many short chains: the partials come from other XCDs' caches, and
+// the latency of each dependent round of loads dominates).
+constexpr int kRedCols = 16, kRedPh = kRW * (64 / kRedCols);
+
 __global__ __launch_bounds__(64 * kRW) void k_cg_reduce(const double *__restrict__ part, int nparts,
                                                         int sp, double *__restrict__ sc, int mode,
                                                         double *__restrict__ resmax) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 64 + lane;
-  __shared__ double red[kRW][64];
+  const int cl = lane % kRedCols, ph = wave * (64 / kRedCols) + lane / kRedCols;
+  const int c = blockIdx.x * kRedCols + cl;
+  __shared__ double red[kRedPh][kRedCols];
   double s = 0.0;
   if (c < sp) {
-#pragma unroll 8
-    for (int b = wave; b < nparts; b += kRW) s += part[(int64_t)b * sp + c];
+#pragma unroll 4
+    for (int b = ph; b < nparts; b += kRedPh) s += part[(int64_t)b * sp + c];
   }
-  red[wave][lane] = s;
+  red[ph][cl] = s;
   __syncthreads();
-  if (wave != 0) return;
+  if (wave != 0 || lane >= kRedCols) return;
   double *yy = sc, *rr = sc + sp, *pq = sc + 2 * sp, *rrn = sc + 3 * sp, *al = sc + 4 * sp,
          *be = sc + 5 * sp;
   if (mode == 1 && blockIdx.x == 0 && lane == 0) *resmax = 0.0;
   if (c >= sp) return;
-  double v = red[0][lane];
-  for (int w = 1; w < kRW; ++w) v += red[w][lane];
+  double v = red[0][cl];
+  for (int h = 1; h < kRedPh; ++h) v += red[h][cl];
   if (mode == 0) {
     yy[c] = v;
     rr[c] = v;
@@ -224,16 +231,16 @@ hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int6
   if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(kWG), 0, s, y, t, r, p, n, sp, part);
-  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp, sc, 0,
-                     (double *)nullptr);
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+                     G, sp, sc, 0, (double *)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, double *resmax,
                            hipStream_t s) {
   if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, nparts, sp, sc, 1,
-                     resmax);
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+                     nparts, sp, sc, 1, resmax);
   return hipGetLastError();
 }
 
@@ -242,8 +249,8 @@ hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, in
   if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kWG), 0, s, t, r, p, q, sc + 4 * sp, n, sp, part);
-  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, G, sp, sc, 2,
-                     resmax);
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+                     G, sp, sc, 2, resmax);
   // blocks a multiple of sp / 64, so blocks * kWG is a multiple of sp
   const int64_t unit = sp / 64;
   int64_t blocks = (n * sp + kWG - 1) / kWG;

@@ -156,6 +156,29 @@ def test_overlap_errors():
         eng.density_forces(D)
 
 
+def test_indefinite_overlap_is_an_error():
+    """A symmetric but indefinite S: diagonal +-1 in equal numbers with H = 0, so every
+    CG direction has p . S p = 0 exactly (alpha stays 0) and the solve cannot converge;
+    the call must end with RFO_E_NUMERIC, not return numbers."""
+    banner("indefinite overlap")
+    import paper_1812_05264_amd as pkg
+    eng = engine_or_skip()
+    n = 16
+    rp = np.arange(n + 1, dtype=np.int64)
+    ci = np.arange(n, dtype=np.int32)
+    S = np.where(np.arange(n) % 2 == 0, 1.0, -1.0).reshape(n, 1, 1)
+    eng.set_hamiltonian(rp, ci, np.zeros((n, 1, 1)), 1, -1.0, 2.0, "fp64")
+    eng.set_overlap(S)
+    eng.set_probes(rademacher(n, 8, config_id=5))
+    with pytest.raises(pkg.RfoError) as e:
+        eng.fermi_moments(0.3, 0.0, 8)
+    assert e.value.status == "RFO_E_NUMERIC"
+    # the context stays usable: a positive definite S runs afterwards
+    eng.set_overlap(np.abs(S))
+    g = eng.fermi_moments(0.3, 0.0, 8)
+    assert np.isfinite(g["N"])
+
+
 @pytest.mark.parametrize("case", ["cu43_s72", "cu19_dense", "sc6_s100", "cu13_p2"])
 def test_overlap_gradient_matches_oracle(case):
     """dF~/dH and dF~/dS with an overlap (Analytical free-energy derivatives, Eq.
