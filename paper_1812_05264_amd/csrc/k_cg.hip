@@ -52,28 +52,39 @@ __device__ __forceinline__ void row_range(int64_t n, int64_t &lo, int64_t &hi) {
 
 }  // namespace
 
-// out[c] = sum_b part[b][c].  A workgroup of kRW waves takes 64 columns; wave w
-// sums the rows b = w, w + kRW, ... in increasing order and the kRW wave sums
-// are then added in wave order, so the result is bitwise reproducible.
+// out[c] = sum_b part[b][c].  A workgroup of kRW waves takes kRedCols columns: lane l of
+// wave w adds, for column l % kRedCols, the rows h, h + kRedPh, ... of phase
+// h = w * (64 / kRedCols) + l / kRedCols in increasing order, and the kRedPh phase sums
+// are then added in phase order, so the result is bitwise reproducible.  Many short
+// chains rather than a few long ones: the partials come from other XCDs' caches, and the
+// latency of each dependent round of loads sets the time.
 constexpr int kRW = 16;
+constexpr int kRedCols = 16, kRedPh = kRW * (64 / kRedCols);
+
+__device__ __forceinline__ double colsum(const double *__restrict__ part, int nparts, int sp,
+                                         double (*red)[kRedCols], int &c) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int cl = lane % kRedCols, ph = wave * (64 / kRedCols) + lane / kRedCols;
+  c = blockIdx.x * kRedCols + cl;
+  double s = 0.0;
+  if (c < sp) {
+#pragma unroll 4
+    for (int b = ph; b < nparts; b += kRedPh) s += part[(int64_t)b * sp + c];
+  }
+  red[ph][cl] = s;
+  __syncthreads();
+  if (threadIdx.x >= kRedCols) return 0.0;  // the sums are formed in the first kRedCols threads
+  double t = red[0][cl];
+  for (int h = 1; h < kRedPh; ++h) t += red[h][cl];
+  return t;
+}
 
 __global__ __launch_bounds__(64 * kRW) void k_colreduce(const double *__restrict__ part, int nparts,
                                                         int sp, double *__restrict__ out) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int c = blockIdx.x * 64 + lane;
-  __shared__ double red[kRW][64];
-  double s = 0.0;
-  if (c < sp) {
-#pragma unroll 8
-    for (int b = wave; b < nparts; b += kRW) s += part[(int64_t)b * sp + c];
-  }
-  red[wave][lane] = s;
-  __syncthreads();
-  if (wave == 0 && c < sp) {
-    double t = red[0][lane];
-    for (int w = 1; w < kRW; ++w) t += red[w][lane];
-    out[c] = t;
-  }
+  __shared__ double red[kRedPh][kRedCols];
+  int c;
+  const double t = colsum(part, nparts, sp, red, c);
+  if (threadIdx.x < kRedCols && c < sp) out[c] = t;
 }
 
 // The row-range kernels below split a workgroup's threads into R = 256 / C row lanes of
@@ -171,34 +182,18 @@ __global__ __launch_bounds__(kWG) void k_cg_direction(const double *__restrict__
 //           columns with yy > 0, by an integer max on the bit patterns (non-negative
 //           doubles order as their bits, and a NaN ends above every finite value).
 // Columns with rr = 0 keep alpha = beta = 0.
-// A workgroup of kRW waves takes kRedCols columns: lane l of wave w adds, for column
-// l % kRedCols, the rows h, h + kRedPh, ... of phase h = w * (64 / kRedCols) + l / kRedCols
-// in order, and the kRedPh phase sums are then added in phase order, so the sums are
-// bitwise reproducible (many short chains: the partials come from other XCDs' caches, and
-// the latency of each dependent round of loads dominates).
-constexpr int kRedCols = 16, kRedPh = kRW * (64 / kRedCols);
-
+// The sums are formed as in k_colreduce.
 __global__ __launch_bounds__(64 * kRW) void k_cg_reduce(const double *__restrict__ part, int nparts,
                                                         int sp, double *__restrict__ sc, int mode,
                                                         double *__restrict__ resmax) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cl = lane % kRedCols, ph = wave * (64 / kRedCols) + lane / kRedCols;
-  const int c = blockIdx.x * kRedCols + cl;
   __shared__ double red[kRedPh][kRedCols];
-  double s = 0.0;
-  if (c < sp) {
-#pragma unroll 4
-    for (int b = ph; b < nparts; b += kRedPh) s += part[(int64_t)b * sp + c];
-  }
-  red[ph][cl] = s;
-  __syncthreads();
-  if (wave != 0 || lane >= kRedCols) return;
+  int c;
+  const double v = colsum(part, nparts, sp, red, c);
+  if (threadIdx.x >= kRedCols) return;
   double *yy = sc, *rr = sc + sp, *pq = sc + 2 * sp, *rrn = sc + 3 * sp, *al = sc + 4 * sp,
          *be = sc + 5 * sp;
-  if (mode == 1 && blockIdx.x == 0 && lane == 0) *resmax = 0.0;
+  if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) *resmax = 0.0;
   if (c >= sp) return;
-  double v = red[0][cl];
-  for (int h = 1; h < kRedPh; ++h) v += red[h][cl];
   if (mode == 0) {
     yy[c] = v;
     rr[c] = v;
@@ -222,7 +217,8 @@ int cg_parts(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(
 int cg_nparts(int64_t n) { return cg_parts(n); }
 
 hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + 63) / 64), dim3(64 * kRW), 0, s, part, nparts, sp, out);
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+                     nparts, sp, out);
   return hipGetLastError();
 }
 
