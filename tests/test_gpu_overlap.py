@@ -33,16 +33,21 @@ def load(eng, H, S):
     eng.set_overlap(S, cg_tol=1e-14)
 
 
-@pytest.mark.parametrize("case", ["cu43", "sc6"])
+# sc6_s340: 340 probes are three 128-column tiles (384 columns), so the CG vector kernels
+# walk their column chunks (128 columns, two row lanes) more than once
+@pytest.mark.parametrize("case", ["cu43", "sc6", "sc6_s340"])
 def test_overlap_matches_oracle(case):
     banner(f"overlap parity {case}")
     eng = engine_or_skip()
     if case == "cu43":
         _, H, S = cu_system(43, 60)
         s, T, mu, p = 72, 0.3, 0.2, 80
-    else:
+    elif case == "sc6":
         H, S = sc_system(6, 61)
         s, T, mu, p = 100, 0.2, 0.1, 120
+    else:
+        H, S = sc_system(6, 65)
+        s, T, mu, p = 340, 0.2, 0.1, 60
     R = rademacher(H.n, s, config_id=62)
     load(eng, H, S)
     eng.set_probes(R)
