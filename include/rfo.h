@@ -89,7 +89,8 @@ int rfo_create(rfo_ctx **out, int device, void *hip_stream);
 void rfo_destroy(rfo_ctx *ctx);
 
 /* Message of the last failed call on ctx ("" if none); valid until the next
- * call on ctx.  With ctx == NULL: the message of the last failed rfo_create. */
+ * call on ctx.  With ctx == NULL: the message of the calling thread's last failed
+ * rfo_create. */
 const char *rfo_last_error(const rfo_ctx *ctx);
 
 /* Sets H (paper: Methods, orthogonal basis S = I; Polynomial approximation,

@@ -7,7 +7,8 @@ using namespace rfo_api;
 
 namespace {
 
-std::string g_create_error;
+// per host thread, so concurrent rfo_create calls do not overwrite each other's message
+thread_local std::string g_create_error;
 
 }  // namespace
 
