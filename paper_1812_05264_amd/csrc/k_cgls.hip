@@ -345,7 +345,6 @@ __global__ __launch_bounds__(kWG) void k_cx_update(double *__restrict__ r,
   for (int c = cl.c0; c < sp; c += cl.cstep) {
     const double al = alpha[c];
     double rr = 0.0;
-#pragma unroll 4
     for (int64_t i = lo + cl.lr; i < hi; i += cl.nl) {
       const int64_t e = i * sp + c;
       const double a = fma(-al, q[e], r[e]);
