@@ -46,8 +46,8 @@ int cgls_solve(rfo_ctx *ctx, CxWork &w, double zr, double zi, double tol, int64_
   const uint64_t *sgn = rhs ? nullptr : ctx->signs ? P<uint64_t>(ctx->sgn) : nullptr;
   const double *rden = rhs ? rhs : ctx->signs ? nullptr : P<double>(ctx->rden);
   double *sc = w.sc;
-  double *yy = sc, *qq = sc + 2 * sp, *ssn = sc + 3 * sp, *rr = sc + 4 * sp, *al = sc + 5 * sp,
-         *be = sc + 6 * sp, *res_d = sc + 7 * sp;
+  double *yy = sc, *ssn = sc + 3 * sp, *rr = sc + 4 * sp, *al = sc + 5 * sp, *be = sc + 6 * sp,
+         *res_d = sc + 7 * sp;
   const double tol2 = tol * tol;
   auto converged = [&](bool &done) -> int {
     HIPCHK(hipMemcpyAsync(ctx->rat_res_h, res_d, sizeof(double), hipMemcpyDeviceToHost,
@@ -79,13 +79,10 @@ int cgls_solve(rfo_ctx *ctx, CxWork &w, double zr, double zi, double tol, int64_
   }
   for (int64_t it = 1; it <= max_iter; ++it) {
     TRY(cspmm(ctx, w, w.p, w.q, zr, zi, w.part));  // q = A p
-    HIPCHK(rfo::launch_colreduce(w.part, grid, sp, qq, ctx->stream));
-    HIPCHK(rfo::launch_cgls_scalars(sc, sp, 1, res_d, ctx->stream));
-    HIPCHK(rfo::launch_cx_update(w.r, w.q, al, n, sp, w.part, ctx->stream));
-    HIPCHK(rfo::launch_colreduce(w.part, G, sp, rr, ctx->stream));
+    HIPCHK(rfo::launch_cgls_reduce(w.part, grid, nullptr, 0, sp, sc, 1, res_d, ctx->stream));
+    HIPCHK(rfo::launch_cx_update(w.r, w.q, al, n, sp, w.part2, ctx->stream));  // |r|^2 partials
     TRY(cspmm(ctx, w, w.r, w.s, zr, -zi, w.part));  // s = A^H r
-    HIPCHK(rfo::launch_colreduce(w.part, grid, sp, ssn, ctx->stream));
-    HIPCHK(rfo::launch_cgls_scalars(sc, sp, 2, res_d, ctx->stream));
+    HIPCHK(rfo::launch_cgls_reduce(w.part, grid, w.part2, G, sp, sc, 2, res_d, ctx->stream));
     HIPCHK(rfo::launch_cx_dir(w.s, w.p, w.x, al, be, n, sp, ctx->stream));  // x += alpha p, new p
     ++ctx->cgls_iters;
     if (it % 4 != 0 && it != max_iter) continue;

@@ -52,39 +52,14 @@ __device__ __forceinline__ void row_range(int64_t n, int64_t &lo, int64_t &hi) {
 
 }  // namespace
 
-// out[c] = sum_b part[b][c].  A workgroup of kRW waves takes kRedCols columns: lane l of
-// wave w adds, for column l % kRedCols, the rows h, h + kRedPh, ... of phase
-// h = w * (64 / kRedCols) + l / kRedCols in increasing order, and the kRedPh phase sums
-// are then added in phase order, so the result is bitwise reproducible.  Many short
-// chains rather than a few long ones: the partials come from other XCDs' caches, and the
-// latency of each dependent round of loads sets the time.
-constexpr int kRW = 16;
-constexpr int kRedCols = 16, kRedPh = kRW * (64 / kRedCols);
-
-__device__ __forceinline__ double colsum(const double *__restrict__ part, int nparts, int sp,
-                                         double (*red)[kRedCols], int &c) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int cl = lane % kRedCols, ph = wave * (64 / kRedCols) + lane / kRedCols;
-  c = blockIdx.x * kRedCols + cl;
-  double s = 0.0;
-  if (c < sp) {
-#pragma unroll 4
-    for (int b = ph; b < nparts; b += kRedPh) s += part[(int64_t)b * sp + c];
-  }
-  red[ph][cl] = s;
-  __syncthreads();
-  if (threadIdx.x >= kRedCols) return 0.0;  // the sums are formed in the first kRedCols threads
-  double t = red[0][cl];
-  for (int h = 1; h < kRedPh; ++h) t += red[h][cl];
-  return t;
-}
-
-__global__ __launch_bounds__(64 * kRW) void k_colreduce(const double *__restrict__ part, int nparts,
-                                                        int sp, double *__restrict__ out) {
-  __shared__ double red[kRedPh][kRedCols];
+// out[c] = sum_b part[b][c] in the fixed order of colsum.
+__global__ __launch_bounds__(64 * kColWaves) void k_colreduce(const double *__restrict__ part,
+                                                              int nparts, int sp,
+                                                              double *__restrict__ out) {
+  __shared__ double red[kColPh][kColCols];
   int c;
   const double t = colsum(part, nparts, sp, red, c);
-  if (threadIdx.x < kRedCols && c < sp) out[c] = t;
+  if (threadIdx.x < kColCols && c < sp) out[c] = t;
 }
 
 // The row-range kernels below split a workgroup's threads into R = 256 / C row lanes of
@@ -183,13 +158,14 @@ __global__ __launch_bounds__(kWG) void k_cg_direction(const double *__restrict__
 //           doubles order as their bits, and a NaN ends above every finite value).
 // Columns with rr = 0 keep alpha = beta = 0.
 // The sums are formed as in k_colreduce.
-__global__ __launch_bounds__(64 * kRW) void k_cg_reduce(const double *__restrict__ part, int nparts,
-                                                        int sp, double *__restrict__ sc, int mode,
-                                                        double *__restrict__ resmax) {
-  __shared__ double red[kRedPh][kRedCols];
+__global__ __launch_bounds__(64 * kColWaves) void k_cg_reduce(const double *__restrict__ part,
+                                                              int nparts, int sp,
+                                                              double *__restrict__ sc, int mode,
+                                                              double *__restrict__ resmax) {
+  __shared__ double red[kColPh][kColCols];
   int c;
   const double v = colsum(part, nparts, sp, red, c);
-  if (threadIdx.x >= kRedCols) return;
+  if (threadIdx.x >= kColCols) return;
   double *yy = sc, *rr = sc + sp, *pq = sc + 2 * sp, *rrn = sc + 3 * sp, *al = sc + 4 * sp,
          *be = sc + 5 * sp;
   if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) *resmax = 0.0;
@@ -217,7 +193,7 @@ int cg_parts(int64_t n) { return (int)std::min<int64_t>(1024, std::max<int64_t>(
 int cg_nparts(int64_t n) { return cg_parts(n); }
 
 hipError_t launch_colreduce(const double *part, int nparts, int sp, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_colreduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+  hipLaunchKernelGGL(k_colreduce, dim3((sp + kColCols - 1) / kColCols), dim3(64 * kColWaves), 0, s, part,
                      nparts, sp, out);
   return hipGetLastError();
 }
@@ -227,7 +203,7 @@ hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int6
   if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_init, dim3(G), dim3(kWG), 0, s, y, t, r, p, n, sp, part);
-  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kColCols - 1) / kColCols), dim3(64 * kColWaves), 0, s, part,
                      G, sp, sc, 0, (double *)nullptr);
   return hipGetLastError();
 }
@@ -235,7 +211,7 @@ hipError_t launch_cg_init(const double *y, double *t, double *r, double *p, int6
 hipError_t launch_cg_alpha(const double *part, int nparts, int sp, double *sc, double *resmax,
                            hipStream_t s) {
   if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kColCols - 1) / kColCols), dim3(64 * kColWaves), 0, s, part,
                      nparts, sp, sc, 1, resmax);
   return hipGetLastError();
 }
@@ -245,7 +221,7 @@ hipError_t launch_cg_update(double *t, double *r, double *p, const double *q, in
   if (sp <= 0 || sp % 64 != 0) return hipErrorInvalidValue;
   const int G = cg_parts(n);
   hipLaunchKernelGGL(k_cg_update, dim3(G), dim3(kWG), 0, s, t, r, p, q, sc + 4 * sp, n, sp, part);
-  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kRedCols - 1) / kRedCols), dim3(64 * kRW), 0, s, part,
+  hipLaunchKernelGGL(k_cg_reduce, dim3((sp + kColCols - 1) / kColCols), dim3(64 * kColWaves), 0, s, part,
                      G, sp, sc, 2, resmax);
   // blocks a multiple of sp / 64, so blocks * kWG is a multiple of sp
   const int64_t unit = sp / 64;

@@ -7,7 +7,8 @@
 // Chebyshev vectors, so the real H_hat multiplies both planes with the same
 // gathers and block values.  Column sums (norms, inner products with the
 // probes) are written as per-workgroup partials and reduced in a fixed order
-// (launch_colreduce), so every scalar is bitwise reproducible.
+// (launch_colreduce, or k_cgls_reduce with the CGLS scalars), so every scalar is
+// bitwise reproducible.
 #include "device_util.h"
 #include "rfo_internal.h"
 
@@ -431,6 +432,43 @@ __global__ __launch_bounds__(kWG) void k_cgls_scalars(double *__restrict__ sc, i
   }
 }
 
+// One CGLS half-iteration's column sums (colsum's fixed order, as launch_colreduce) and
+// scalars in one kernel, on sc = [yy | gam | qq | ssn | rr | alpha | beta]:
+//   mode 1: qq = sums of pa [na][sp]; alpha = gam / qq; *resmax = 0 for mode 2.
+//   mode 2: ssn = sums of pa [na][sp], rr = sums of pb [nb][sp]; beta = ssn / gam,
+//           gam = ssn, *resmax = max_c rr / yy over columns with yy > 0 (an integer max
+//           on the bit patterns of non-negative doubles), +inf for a non-finite rr or ssn.
+__global__ __launch_bounds__(64 * kColWaves) void k_cgls_reduce(const double *__restrict__ pa, int na,
+                                                                const double *__restrict__ pb, int nb,
+                                                                int sp, double *__restrict__ sc,
+                                                                int mode,
+                                                                double *__restrict__ resmax) {
+  __shared__ double red_a[kColPh][kColCols], red_b[kColPh][kColCols];
+  int c;
+  const double va = colsum(pa, na, sp, red_a, c);
+  const double vb = mode == 2 ? colsum(pb, nb, sp, red_b, c) : 0.0;
+  if (threadIdx.x >= kColCols) return;
+  double *yy = sc, *gam = sc + sp, *qq = sc + 2 * sp, *ssn = sc + 3 * sp, *rr = sc + 4 * sp,
+         *al = sc + 5 * sp, *be = sc + 6 * sp;
+  if (mode == 1 && blockIdx.x == 0 && threadIdx.x == 0) *resmax = 0.0;
+  if (c >= sp) return;
+  if (mode == 1) {
+    qq[c] = va;
+    al[c] = (gam[c] > 0.0 && va > 0.0) ? gam[c] / va : 0.0;
+    return;
+  }
+  ssn[c] = va;
+  rr[c] = vb;
+  be[c] = gam[c] > 0.0 ? va / gam[c] : 0.0;
+  gam[c] = va;
+  double m = -1.0;
+  if (yy[c] > 0.0) m = vb / yy[c];
+  if (!isfinite(vb) || !isfinite(va)) m = HUGE_VAL;
+  if (m >= 0.0)
+    atomicMax(reinterpret_cast<unsigned long long *>(resmax),
+              (unsigned long long)__double_as_longlong(m));
+}
+
 // N, E, F of the rational estimate (one workgroup, fixed order):
 //   per column c:  N_c = f0 m0 + 2 Re sum_k cn_k rho_kc
 //                  E_c = f0 h + ew m0 + 2 Re sum_k ce_k rho_kc
@@ -532,6 +570,14 @@ hipError_t launch_cx_scale(const double *src, double *dst, int64_t n, double alp
 
 hipError_t launch_cgls_scalars(double *sc, int sp, int mode, double *resmax, hipStream_t s) {
   hipLaunchKernelGGL(k_cgls_scalars, dim3(1), dim3(kWG), 0, s, sc, sp, mode, resmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgls_reduce(const double *pa, int na, const double *pb, int nb, int sp, double *sc,
+                              int mode, double *resmax, hipStream_t s) {
+  if (sp <= 0 || (mode != 1 && mode != 2) || (mode == 2 && !pb)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cgls_reduce, dim3((sp + kColCols - 1) / kColCols), dim3(64 * kColWaves), 0, s,
+                     pa, na, pb, nb, sp, sc, mode, resmax);
   return hipGetLastError();
 }
 

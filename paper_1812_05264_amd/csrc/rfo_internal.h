@@ -285,6 +285,12 @@ hipError_t launch_cx_pdot(const uint64_t *sgn, const double *rden, const double 
 hipError_t launch_cx_scale(const double *src, double *dst, int64_t n, double alpha, hipStream_t s);
 // mode 0: gam = ssn, *resmax;  1: alpha = gam / qq;  2: beta = ssn / gam, gam = ssn, *resmax
 hipError_t launch_cgls_scalars(double *sc, int sp, int mode, double *resmax, hipStream_t s);
+// the column sums and scalars of one half-iteration in one kernel: mode 1 reduces pa
+// [na][sp] into qq and forms alpha (and zeroes *resmax); mode 2 reduces pa into ssn and
+// pb [nb][sp] into rr and forms beta, gam and *resmax (the values of launch_colreduce
+// followed by launch_cgls_scalars)
+hipError_t launch_cgls_reduce(const double *pa, int na, const double *pb, int nb, int sp, double *sc,
+                              int mode, double *resmax, hipStream_t s);
 struct RationalScalars {
   double f0, ew, g0, g1;   // constant of f, 2 Re sum_k w_k, constant and slope of g
 };
