@@ -3,6 +3,7 @@
 // the pieces of a conjugate-gradient solve S t = y for a block of probe columns
 // (one independent CG per column; the matrix-vector product is the step kernel
 // with S as its matrix).  Column reductions are two-pass and in a fixed order.
+#include "colsum.h"
 #include "device_util.h"
 #include "rfo_internal.h"
 

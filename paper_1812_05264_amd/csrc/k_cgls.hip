@@ -9,6 +9,7 @@
 // probes) are written as per-workgroup partials and reduced in a fixed order
 // (launch_colreduce, or k_cgls_reduce with the CGLS scalars), so every scalar is
 // bitwise reproducible.
+#include "colsum.h"
 #include "device_util.h"
 #include "rfo_internal.h"
 
