@@ -101,6 +101,44 @@ def _host(a, dtype):
     return np.ascontiguousarray(a, dtype=dtype)
 
 
+def _numel(a):
+    return a.numel() if isinstance(a, torch.Tensor) else int(np.asarray(a).size)
+
+
+def _need(a, n, what):
+    """The C ABI takes plain pointers: a buffer of the wrong size would be read or
+    written past its end, so every size is checked here.  n = 0 (no Hamiltonian
+    yet) checks nothing: the library then rejects the call by its state."""
+    if a is not None and n > 0 and _numel(a) != n:
+        raise ValueError(f"{what} must hold {n} values (got {_numel(a)})")
+
+
+def _out_f64(a, n, what):
+    """A caller-supplied output buffer: FP64, contiguous, n values (None passes)."""
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64:
+            raise TypeError(f"{what} must be float64")
+    elif np.asarray(a).dtype != np.float64:
+        raise TypeError(f"{what} must be float64")
+    _need(a, n, what)
+    return a
+
+
+def _in_f64(a, n, what):
+    """An input block array: torch tensors stay where they are (FP64, made
+    contiguous), anything else becomes a contiguous FP64 host array; n values."""
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64:
+            raise TypeError(f"{what} must be float64")
+        a = a.contiguous()
+    else:
+        a = np.ascontiguousarray(a, dtype=np.float64)
+    _need(a, n, what)
+    return a
+
+
 def _complex_pairs(a):
     a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
     return np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))
@@ -178,27 +216,29 @@ class Engine:
         """row_ptr/col_idx: host arrays (None, None keeps the pattern); values: FP64
         [nnzb, bd, bd] numpy array or torch tensor (host or device).  e_min >= e_max
         asks for the widened Gershgorin interval."""
+        bd = int(block_dim)
         if row_ptr is None and col_idx is None:
             rp = ci = None
             nb = self.n_block_rows
+            nnzb = self.nnzb
         else:
-            rp = _host(row_ptr, np.int64)
-            ci = _host(col_idx, np.int32)
+            rp = _host(row_ptr, np.int64).ravel()
+            ci = _host(col_idx, np.int32).ravel()
+            if rp.shape[0] < 2:
+                raise ValueError("row_ptr must hold n_block_rows + 1 >= 2 entries")
             nb = rp.shape[0] - 1
-        if isinstance(values, torch.Tensor):
-            if values.dtype != torch.float64:
-                raise TypeError("values must be float64")
-            vals = values.contiguous()
-        else:
-            vals = np.ascontiguousarray(values, dtype=np.float64)
+            nnzb = int(rp[-1])
+            _need(ci, nnzb, "col_idx")
+        # other block sizes are rejected by the library before it reads the values
+        vals = _in_f64(values, nnzb * bd * bd if bd in (1, 9) else 0, "values")
         self._keep = (rp, ci, vals)
         self._check(self._lib.rfo_set_hamiltonian(self._ctx, nb, int(block_dim), _ptr(rp), _ptr(ci),
                                                   _ptr(vals), float(e_min), float(e_max),
                                                   PRECISIONS[precision]))
         self._keep = None
         self.n_block_rows = nb
-        self.block_dim = int(block_dim)
-        self.nnzb = int(vals.shape[0]) if ci is None else int(ci.shape[0])
+        self.block_dim = bd
+        self.nnzb = nnzb
         self.precision = precision
         return self.interval()
 
@@ -214,8 +254,13 @@ class Engine:
 
     # -- rfo_set_probes -------------------------------------------------------------
     def set_probes(self, R, weights=None):
+        """R [n, s] (n = n_block_rows * block_dim rows, s probes); weights [s] or None."""
         R = _host(R, np.float64)
+        n = self.n_block_rows * self.block_dim
+        if R.ndim != 2 or (n > 0 and R.shape[0] != n):
+            raise ValueError(f"R must be [{n}, s] (got {list(R.shape)})")
         w = None if weights is None else _host(weights, np.float64)
+        _need(w, R.shape[1], "weights")
         self._check(self._lib.rfo_set_probes(self._ctx, int(R.shape[1]), _ptr(R), _ptr(w)))
         self.n_probes = int(R.shape[1])
 
@@ -223,6 +268,11 @@ class Engine:
         """One sample of the multi-color ensemble, built by the library (weights one)."""
         col = np.ascontiguousarray(colours, dtype=np.int32)
         sg = np.ascontiguousarray(signs, dtype=np.float64)
+        n = self.n_block_rows * self.block_dim
+        if n > 0 and (int(n_orb) < 1 or n % int(n_orb) != 0):
+            raise ValueError(f"n_orb must divide the {n} rows")
+        _need(col, n // int(n_orb) if n > 0 else 0, "colours")
+        _need(sg, n, "signs")
         self._check(self._lib.rfo_set_colored_probes(self._ctx, _ptr(col), int(n_orb), _ptr(sg)))
         self.n_probes = (int(col.max()) + 1) * int(n_orb)
 
@@ -232,7 +282,7 @@ class Engine:
         density_out may be a preallocated FP64 torch tensor (host or device)."""
         mom = np.empty((self.n_probes, int(n_terms))) if moments else None
         nef = np.empty(3)
-        dens = density_out
+        dens = _out_f64(density_out, self.nnzb * self.block_dim * self.block_dim, "density_out")
         if density and dens is None:
             dens = np.empty((self.nnzb, self.block_dim, self.block_dim))
         self._check(self._lib.rfo_fermi_moments(self._ctx, float(T), float(mu), int(n_terms),
@@ -253,7 +303,7 @@ class Engine:
     # -- rfo_energy_and_dEdH --------------------------------------------------------
     def energy_and_dEdH(self, T, mu, n_terms, gradient=True, dFdH_out=None):
         nef = np.empty(3)
-        g = dFdH_out
+        g = _out_f64(dFdH_out, self.nnzb * self.block_dim * self.block_dim, "dFdH_out")
         if gradient and g is None:
             g = np.empty((self.nnzb, self.block_dim, self.block_dim))
         self._check(self._lib.rfo_energy_and_dEdH(self._ctx, float(T), float(mu), int(n_terms),
@@ -262,10 +312,8 @@ class Engine:
 
     # -- rfo_hf_forces --------------------------------------------------------------
     def hf_forces(self, dHdR):
-        if isinstance(dHdR, torch.Tensor):
-            d = dHdR.contiguous()
-        else:
-            d = np.ascontiguousarray(dHdR, dtype=np.float64)
+        """dHdR [nnzb, 3, bd, bd] (host or device FP64): forces [n_block_rows, 3]."""
+        d = _in_f64(dHdR, self.nnzb * 3 * self.block_dim * self.block_dim, "dHdR")
         out = np.empty((self.n_block_rows, 3))
         self._check(self._lib.rfo_hf_forces(self._ctx, _ptr(d), _ptr(out)))
         return out
@@ -273,8 +321,11 @@ class Engine:
     def hf_forces_overlap(self, dHdR, dSdR):
         """-(sum <dF/dH, dH/dR_a> + sum <dF/dS, dS/dR_a>) from the last gradient with an
         overlap, [n_block_rows, 3]."""
+        nd = self.nnzb * 3 * self.block_dim * self.block_dim
         dH = _host(dHdR, np.float64)
         dS = None if dSdR is None else _host(dSdR, np.float64)
+        _need(dH, nd, "dHdR")
+        _need(dS, nd, "dSdR")
         out = np.empty((self.n_block_rows, 3))
         self._check(self._lib.rfo_hf_forces_overlap(self._ctx, _ptr(dH), _ptr(dS), _ptr(out)))
         return out
@@ -289,6 +340,7 @@ class Engine:
     def set_overlap(self, S_values=None, cg_tol=1e-13):
         """Overlap S [nnzb, bd, bd] on H's pattern (None: S = I)."""
         S = None if S_values is None else _host(S_values, np.float64)
+        _need(S, self.nnzb * self.block_dim * self.block_dim, "S_values")
         self._check(self._lib.rfo_set_overlap(self._ctx, _ptr(S), float(cg_tol)))
 
     def density_q(self):
@@ -299,8 +351,11 @@ class Engine:
 
     def density_forces(self, dHdR, dSdR=None):
         """-(tr[P dH/dR_a] - tr[Q dS/dR_a]) from the last density blocks, [n_block_rows, 3]."""
+        nd = self.nnzb * 3 * self.block_dim * self.block_dim
         dH = _host(dHdR, np.float64)
         dS = None if dSdR is None else _host(dSdR, np.float64)
+        _need(dH, nd, "dHdR")
+        _need(dS, nd, "dSdR")
         out = np.empty((self.n_block_rows, 3))
         self._check(self._lib.rfo_density_forces(self._ctx, _ptr(dH), _ptr(dS), _ptr(out)))
         return out
@@ -318,10 +373,11 @@ class Engine:
         npol = z.shape[0]
         nef = np.empty(3)
         its = np.empty(npol, dtype=np.int64)
-        dens = density_out
+        nv = self.nnzb * self.block_dim * self.block_dim
+        dens = _out_f64(density_out, nv, "density_out")
         if density and dens is None:
             dens = np.empty((self.nnzb, self.block_dim, self.block_dim))
-        g = dFdH_out
+        g = _out_f64(dFdH_out, nv, "dFdH_out")
         if gradient and g is None:
             g = np.empty((self.nnzb, self.block_dim, self.block_dim))
         self._check(self._lib.rfo_rational_estimate(

@@ -101,3 +101,35 @@ def test_tuning_keys_and_values_are_validated():
         eng._check(eng._lib.rfo_set_tuning(eng._ctx, 99, 1))
     for key in eng.TUNING:
         eng.set_tuning(key, -1)
+
+
+def test_binding_refuses_buffers_of_the_wrong_size():
+    """Wrong sizes and types never reach the C ABI (which would read or write past
+    the buffer): the binding raises first, and the context stays usable."""
+    banner("binding buffer checks")
+    import torch
+    eng = engine_or_skip()
+    H = simple_cubic(4)
+    load_hamiltonian(eng, H)
+    n = H.n
+    with pytest.raises(ValueError):
+        eng.set_hamiltonian(H.row_ptr, H.col_idx, H.values[:-1], 1, H.e_min, H.e_max)
+    with pytest.raises(ValueError):
+        eng.set_hamiltonian(H.row_ptr, H.col_idx[:-1], H.values, 1, H.e_min, H.e_max)
+    with pytest.raises(ValueError):
+        eng.set_probes(rademacher(n - 1, 4))
+    with pytest.raises(ValueError):
+        eng.set_probes(rademacher(n, 4), weights=np.ones(3))
+    eng.set_probes(rademacher(n, 4))
+    with pytest.raises(TypeError):
+        eng.fermi_moments(0.1, 0.0, 10, density_out=torch.zeros(H.nnzb, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        eng.fermi_moments(0.1, 0.0, 10, density_out=np.zeros(H.nnzb - 1))
+    with pytest.raises(ValueError):
+        eng.energy_and_dEdH(0.1, 0.0, 10, dFdH_out=np.zeros(H.nnzb + 1))
+    with pytest.raises(ValueError):
+        eng.hf_forces(np.zeros((H.nnzb, 2, 1, 1)))
+    with pytest.raises(ValueError):
+        eng.set_overlap(np.ones(H.nnzb - 1))
+    g = eng.fermi_moments(0.1, 0.0, 10, density=True)
+    assert np.isfinite(g["N"]) and g["density"].shape == (H.nnzb, 1, 1)
