@@ -191,6 +191,26 @@ def test_gradient_matches_oracle(name, doubling):
         assert np.max(np.abs(fg.sum(axis=0))) < 1e-10 * np.max(np.abs(fg))
 
 
+@pytest.mark.parametrize("doubling", [True, False])
+def test_gradient_of_a_one_term_series_is_zero(doubling):
+    """p = 1 keeps only the constant term beta_0 T_0(H_hat) = beta_0 I, whose trace does
+    not depend on H: F matches the oracle and every gradient block is exactly zero (the
+    smallest series of the degenerate kind; p = 2..5 are in GRAD_CASES)."""
+    banner(f"one-term gradient doubling={doubling}")
+    eng = engine_or_skip()
+    H = cu_cluster(55, config_id=26).bsr()
+    R = rademacher(H.n, 3, config_id=500)
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    eng.set_moment_doubling(doubling)
+    g = eng.energy_and_dEdH(0.3, 0.4, 1)
+    o = est.estimate(H, R, 0.3, 0.4, 1, gradient=True)
+    assert np.all(o["dFdH"] == 0.0)
+    for key in ("N", "E", "F"):
+        assert abs(g[key] - o[key]) <= TOL * max(1.0, abs(o[key])), key
+    assert np.all(g["dFdH"] == 0.0)
+
+
 def test_gradient_symmetric_and_deterministic():
     banner("gradient symmetry and determinism")
     eng = engine_or_skip()
