@@ -162,6 +162,8 @@ GRAD_CASES = {
     "cu55_p5": (lambda: cu_cluster(55, config_id=26), 3, 0.3, 0.4, 5),
     # several checkpoint segments with the doubling (K = 150, segments of 13)
     "sc6_p301": (lambda: simple_cubic(6, disorder=0.3, config_id=30), 5, 0.1, 0.2, 301),
+    # one probe: 63 of the 64 columns are padding
+    "cu13_s1": (lambda: cu_cluster(13, config_id=27), 1, 0.3, 0.2, 40),
 }
 
 
