@@ -66,3 +66,29 @@ def test_noalloc_refuses_oversized_work_and_repeats():
     check_moments(second["moments"], o["moments"])
     with pytest.raises(pkg.RfoError):
         eng.traces_at(0.1, 0.0)              # the moments stay in the shared scratch array
+
+
+def test_noalloc_dense_probes_with_a_padded_last_tile():
+    """Dense (not +-1) probes, stored in FP64, and 150 of them: 256 columns whose last
+    128-column tile holds 22 real probes (rfo_fermi_moments runs those as a batch of
+    their own; the allocation-free call keeps one block).  Both match the oracle at the
+    parity bar, twice in a row."""
+    banner("noalloc: dense probes, padded last tile")
+    eng = engine_or_skip()
+    H = cu_cluster(55, config_id=44).bsr()
+    R = rademacher(H.n, 150, config_id=745) * (1.0 + 0.25 * np.cos(np.arange(H.n)))[:, None]
+    load_hamiltonian(eng, H)
+    eng.set_probes(R)
+    T, mu, p = 0.3, 0.2, 90
+    o = est.estimate(H, R, T, mu, p)
+    for dbl in (True, False):
+        eng.set_moment_doubling(dbl)
+        a = eng.fermi_moments(T, mu, p, moments=True)
+        b = eng.fermi_moments_noalloc(T, mu, p, moments=True)
+        c = eng.fermi_moments_noalloc(T, mu, p, moments=True)
+        check_moments(a["moments"], o["moments"], what=f"batched dbl={dbl}")
+        check_moments(b["moments"], o["moments"], what=f"noalloc dbl={dbl}")
+        assert np.array_equal(b["moments"], c["moments"])
+        for k in ("N", "E", "F"):
+            assert abs(b[k] - o[k]) <= 1e-10 * max(1.0, abs(o[k])), (k, dbl)
+    eng.set_moment_doubling(True)
