@@ -148,7 +148,12 @@ int rfo_fermi_moments(rfo_ctx *ctx, double T, double mu, int64_t n_terms,
 /* rfo_fermi_moments without density and without any device allocation, for
  * callers that cannot allocate (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  The same kernels in the same order:
- * the results equal those of rfo_fermi_moments with density_out = NULL.  The
+ * the results equal those of rfo_fermi_moments with density_out = NULL, except
+ * when that call runs a mostly-padding last probe tile as a batch of its own
+ * (more than 128 probes, s mod 128 in 1..64): this call keeps one block, and the
+ * two agree to rounding.  Like the other calls it waits for its work before it
+ * returns (it reads the status flag and copies N, E, F out), so it allocates
+ * nothing but is not itself recorded into a HIP graph.  The
  * work memory comes from a fixed device array of the library, 128 MiB per device
  * (held from the first such call on a device until the process ends), shared by
  * every call on that device: calls that overlap on one device race.  It must
